@@ -1,0 +1,209 @@
+/*
+ * crsolve.h -- C ABI of the MI355X (gfx950) solver for the multi-resolution
+ * Wiener-filter / constrained-realization system of Seljebotn et al.,
+ * "Multi-resolution Bayesian CMB component separation through
+ * Wiener-filtering with a pseudo-inverse preconditioner" (arXiv:1710.00621).
+ *
+ * The library solves A x = b with (Sect. 2.3, eq:A)
+ *     A = S^-1 + sum_nu P_nu^T N_nu^-1 P_nu,   P_nu = Y_nu B_nu q_{nu,k}  (eq:P)
+ * by preconditioned conjugate gradients, preconditioned either with the
+ * pseudo-inverse preconditioner M_PI = U^+ T^+ (U^+)^T (Sect. 3.3,
+ * eq:fullmodel-preconditioner) or with the block-diagonal comparison
+ * preconditioner M_diag = (U^T diag(T) U)^-1 (Sect. 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns CRS_OK (0) or a negative CRS_E* code and
+ *   never throws.  On failure a message is kept per thread (crs_last_error).
+ *   Arguments are validated on the host before anything is launched.
+ * Precision: float64 throughout.  Architecture: gfx950 only.
+ * Harmonic vectors: real orthonormal spherical harmonics (no Condon-Shortley
+ *   sign; Y^c_lm = sqrt2 lambda_lm cos m phi, Y^s_lm = sqrt2 lambda_lm sin m phi)
+ *   packed m-major: [m=0: l=0..L] then for m=1..L [cos: l=m..L][sin: l=m..L];
+ *   (L+1)^2 doubles.  A component vector is the concatenation over
+ *   components k of their (L_k+1)^2 blocks; n = sum_k (L_k+1)^2.
+ * Maps: ring-major pixel order (HEALPix RING order), north to south.
+ * Memory: "device" pointers are HIP device memory owned by the caller; the
+ *   library never frees them nor keeps them past the call.  "host" pointers
+ *   are ordinary host memory.  Handles own their tables and workspaces.
+ * Streams: work is enqueued on the given stream (0 = null stream).  Calls
+ *   on one handle must not overlap in time (the handle's workspace is
+ *   shared); distinct handles are independent.
+ * Allocation: create calls allocate; apply/solve calls allocate nothing
+ *   once a handle has seen the largest nrhs it is used with (workspaces grow
+ *   on the first call with a larger nrhs).  sht_synth / sht_adjoint allocate
+ *   per-(grid, lmax) tables on their first call for that pair.
+ */
+#ifndef CRSOLVE_H
+#define CRSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* crs_stream;   /* hipStream_t */
+
+typedef struct crs_grid_s*  crs_grid;
+typedef struct crs_model_s* crs_model;
+typedef struct crs_batch_s* crs_batch;
+
+enum {
+  CRS_OK = 0,
+  CRS_EINVAL = -1,        /* invalid argument (message says which) */
+  CRS_ENOMEM = -2,        /* device or host allocation failed */
+  CRS_EHIP = -3,          /* a HIP runtime call failed */
+  CRS_ENOTCONV = -4,      /* PCG hit maxiter; x holds the last iterate */
+  CRS_EBREAKDOWN = -5,    /* PCG breakdown: p.Ap <= 0, r.z <= 0 or non-finite */
+  CRS_EUNSUPPORTED = -6   /* valid request outside what this build supports */
+};
+
+enum { CRS_PRECOND_NONE = 0, CRS_PRECOND_DIAG = 1, CRS_PRECOND_PINV = 2 };
+enum { CRS_MODE_WF = 0, CRS_MODE_CR = 1 };
+
+const char* crs_strerror(int status);
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes).  Returns the status code of that error. */
+int crs_last_error(char* buf, size_t n);
+/* Library version string (static storage). */
+const char* crs_version(void);
+
+/* ------------------------------------------------------------------ grids
+ * Ring grids of Sect. 2.1 / 2.2: HEALPix RING (Gorski et al. 2005) for sky
+ * maps and Gauss-Legendre (roots of P_nrings, north to south, phi0 = 0).
+ * Ring lengths are limited to 4096 pixels (Nside <= 1024, nphi <= 4096).
+ */
+int crs_grid_healpix(int nside, crs_grid* out);
+int crs_grid_gauss_legendre(int nrings, int nphi, crs_grid* out);
+/* host out-params; either may be NULL */
+int crs_grid_info(crs_grid g, int* nrings, int64_t* npix);
+/* Pixel centres (z = cos theta, phi) in ring order; host arrays of npix. */
+int crs_grid_pixel_centres(crs_grid g, double* z, double* phi);
+/* Quadrature weights, the diagonal of W (Sect. 2.1); host array of npix.
+ * HEALPix: 4 pi / Npix.  Gauss-Legendre: w_r 2 pi / nphi. */
+int crs_grid_weights(crs_grid g, double* w);
+int crs_grid_destroy(crs_grid g);
+
+/* -------------------------------------------------------------- transforms
+ * sht_synth: map = Y alm, spherical harmonic synthesis (Sect. 2.1).
+ * sht_adjoint: alm = Y^T map, the literal transpose of synthesis (adjoint
+ *   synthesis, Sect. 3.2; not analysis, which is Y^T W).
+ * alm: device, nmaps x alm_stride doubles, each map (lmax+1)^2 packed.
+ * map: device, nmaps x map_stride doubles, each map npix pixels.
+ * Any lmax >= 0 is accepted on any grid; rings with fewer than 2 lmax + 1
+ * pixels alias (m folded modulo nphi), exactly like the dense matrix.
+ * Strides must be >= the per-map length.  Errors: CRS_EINVAL on NULL
+ * pointers, lmax < 0, nmaps < 1, short strides.
+ */
+int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_stride,
+              double* map, int64_t map_stride, crs_stream s);
+int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride,
+                double* alm, int64_t alm_stride, crs_stream s);
+
+/* ------------------------------------------------------------------ model
+ * One band (sky map) nu of Sect. 2.2: grid, band-limit L_nu, beam b_{nu,l}
+ * (host, lmax+1; modes above L_nu are not represented), inverse-noise map
+ * tau = diag(N_nu^-1) (host, npix, >= 0; 0 marks masked pixels) and the
+ * mixing scalars q_{nu,k} (host, ncomp) of the spatially constant mixing
+ * Q~_{nu,k} = q_{nu,k} I (Sect. 3.3).  tau, beam and q are copied.
+ */
+typedef struct {
+  crs_grid grid;
+  int lmax;
+  const double* beam;
+  const double* tau;
+  const double* q;
+} crs_band_desc;
+
+/* The model: ncomp components with band-limits L_k (host array) and prior
+ * inverse spectra C_{k,l}^-1 (host pointers, each L_k+1 values >= 0; 0 means
+ * no prior for that mode, Sect. 3.3 under eq:U-prior), plus nbands bands.
+ * Creation computes alpha_nu (App. A.1, eq:optimal-alpha), the blocks U_l^+
+ * (Sect. 3.3) and the T^+ pixel weights alpha^2 w^2 tau^+ (tau^+ = 1/tau where
+ * tau > 0, else 0), and with flags & CRS_MODEL_DIAG also the M_diag blocks.
+ */
+enum { CRS_MODEL_DIAG = 1 };
+typedef struct {
+  int ncomp;
+  const int* lmax_comp;
+  const double* const* inv_cl;
+  int nbands;
+  const crs_band_desc* bands;
+  int flags;
+} crs_model_desc;
+
+int crs_model_create(const crs_model_desc* d, crs_stream s, crs_model* out);
+int crs_model_destroy(crs_model m);
+/* n = sum_k (L_k+1)^2 */
+int crs_model_size(crs_model m, int64_t* n);
+/* alpha_nu^2 for every band (host array of nbands). */
+int crs_model_alpha2(crs_model m, double* alpha2);
+/* Replace the mixing matrix q (host, nbands x ncomp, row = band) and
+ * recompute U^+ (and M_diag if present). */
+int crs_model_set_mixing(crs_model m, const double* q, crs_stream s);
+
+/* Operators on nrhs stacked component vectors (device, nrhs x n, contiguous).
+ * apply_A: y = A x (eq:A).  apply_pinv_precond: z = M_PI r.
+ * apply_diag_precond: z = M_diag r (needs CRS_MODEL_DIAG). */
+int apply_A(crs_model m, int nrhs, const double* x, double* y, crs_stream s);
+int apply_pinv_precond(crs_model m, int nrhs, const double* r, double* z, crs_stream s);
+int apply_diag_precond(crs_model m, int nrhs, const double* r, double* z, crs_stream s);
+
+/* Preconditioned CG (Sect. 2.3) on nrhs independent right-hand sides.
+ * b: device nrhs x n.  x: device nrhs x n, initial guess on entry (use zeros
+ * for the paper's x_1 = 0), solution on exit.  Each RHS stops when its
+ * recursive residual |r|/|b| <= rtol; the true residual is then formed once
+ * and the RHS restarts from its iterate if that fails rtol.
+ * iters, relres: host arrays of nrhs (iterations used, final true relative
+ * residual), may be NULL.  The host reads one scalar per iteration to test
+ * convergence.  Returns CRS_ENOTCONV if any RHS hit maxiter, CRS_EBREAKDOWN
+ * on breakdown (x then holds the last good iterate of that RHS).
+ * history: optional host array of maxiter * nrhs recursive relative residuals
+ * (row = iteration), may be NULL. */
+int pcg_solve(crs_model m, int precond, int nrhs, const double* b, double* x,
+              double rtol, int maxiter, int* iters, double* relres, double* history,
+              crs_stream s);
+
+/* Right-hand side (Sect. 2.3, with S^-1 omega_2 read as S^-1/2 omega_2):
+ *   b = sum_nu P_nu^T (tau_nu d_nu + tau_nu^1/2 omega1_nu) + C^-1/2 omega2.
+ * d, omega1: host arrays of nbands device pointers, each nrhs x npix_nu
+ * (the array itself or any entry may be NULL = zero).  omega2: device
+ * nrhs x n or NULL.  b: device nrhs x n. */
+int build_rhs(crs_model m, int nrhs, const double* const* d, const double* const* omega1,
+              const double* omega2, double* b, crs_stream s);
+
+/* Constrained realization (mode CRS_MODE_CR) or Wiener filter (CRS_MODE_WF):
+ * draws omega_1, omega_2 on the device with Philox4x64-10 (key = (seed,
+ * stream id), counter = (i/4, rhs, 0, 0), Box-Muller), builds b and runs
+ * pcg_solve from x = 0.  d as in build_rhs.  x: device nrhs x n. */
+int constrained_realization(crs_model m, int nrhs, const double* const* d, uint64_t seed,
+                            int mode, int precond, double rtol, int maxiter, double* x,
+                            int* iters, double* relres, crs_stream s);
+
+/* P_nu x for every band (eq:P): maps is a host array of nbands device
+ * pointers, each receiving nrhs x npix_nu doubles.  x: device nrhs x n.
+ * (Used to synthesise data d = P s + n.) */
+int crs_model_project(crs_model m, int nrhs, const double* x, double* const* maps, crs_stream s);
+
+/* Device normals of the library's Philox stream (the omega draws of
+ * constrained_realization): out[i] for i < n, device array. */
+int crs_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs, int64_t n, double* out,
+                       crs_stream s);
+
+/* ------------------------------------------------------------- profiling
+ * With profiling on, every Legendre-stage kernel launch is bracketed by HIP
+ * events on its stream; crs_kernel_stats synchronises on those events and
+ * reports, per kernel family ("legendre_synth", "legendre_adjoint",
+ * "ring_fft"), launches, summed device time and summed algorithmic work
+ * (flops for Legendre, bytes for ring_fft). */
+int crs_set_profiling(int on);
+int crs_kernel_stats(const char* family, int64_t* launches, double* total_ms,
+                     double* total_work);
+int crs_kernel_stats_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRSOLVE_H */

@@ -73,6 +73,11 @@ class LegendreSweep:
             self._mant = mant
             self._exp = self._exp + e.astype(np.int64)
 
+    def skip_to(self, m):
+        """Advance the carried start value so that the next table is for m."""
+        while self._m + 1 < m:
+            self._advance_start()
+
     def table(self, m):
         if m != self._m + 1:
             raise ValueError("LegendreSweep.table must be called with m = 0, 1, 2, ...")

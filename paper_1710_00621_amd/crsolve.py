@@ -1,0 +1,333 @@
+"""Python binding of the crsolve C ABI on torch tensors.
+
+Every operation runs in the HIP library; this module only checks tensor
+shapes, device and dtype, passes raw pointers and the current torch stream,
+and turns status codes into exceptions.  Tensors are float64, contiguous and
+on a CUDA (HIP) device.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+c_double_p = _lib.c_double_p
+
+
+def _stream(dev=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev_f64(t, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(c_double_p)
+
+
+def nalm(lmax):
+    return (lmax + 1) * (lmax + 1)
+
+
+class Grid:
+    """HEALPix RING or Gauss-Legendre ring grid (library handle)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        nr = ctypes.c_int()
+        npix = ctypes.c_int64()
+        check(lib().crs_grid_info(self._h, ctypes.byref(nr), ctypes.byref(npix)))
+        self.nring = nr.value
+        self.npix = npix.value
+
+    @classmethod
+    def healpix(cls, nside):
+        h = ctypes.c_void_p()
+        check(lib().crs_grid_healpix(int(nside), ctypes.byref(h)))
+        g = cls(h)
+        g.spec = ("healpix", int(nside))
+        return g
+
+    @classmethod
+    def gauss_legendre(cls, nrings, nphi):
+        h = ctypes.c_void_p()
+        check(lib().crs_grid_gauss_legendre(int(nrings), int(nphi), ctypes.byref(h)))
+        g = cls(h)
+        g.spec = ("gl", int(nrings), int(nphi))
+        return g
+
+    @classmethod
+    def from_spec(cls, spec):
+        if spec[0] == "healpix":
+            return cls.healpix(spec[1])
+        if spec[0] == "gl":
+            return cls.gauss_legendre(spec[1], spec[2])
+        raise ValueError(spec)
+
+    def pixel_centres(self):
+        z = np.empty(self.npix)
+        phi = np.empty(self.npix)
+        check(lib().crs_grid_pixel_centres(self._h, z.ctypes.data_as(c_double_p),
+                                           phi.ctypes.data_as(c_double_p)))
+        return z, phi
+
+    def weights(self):
+        w = np.empty(self.npix)
+        check(lib().crs_grid_weights(self._h, w.ctypes.data_as(c_double_p)))
+        return w
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().crs_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _as2d(t):
+    return (t.unsqueeze(0), True) if t.dim() == 1 else (t, False)
+
+
+def sht_synth(grid, lmax, alm, out=None):
+    """Y alm (Sect. 2.1): alm [nmaps, (lmax+1)^2] or [(lmax+1)^2] -> maps."""
+    a, sq = _as2d(alm)
+    if a.shape[1] != nalm(lmax):
+        raise ValueError("alm has the wrong length for lmax")
+    nm = a.shape[0]
+    if out is None:
+        out = torch.empty((nm, grid.npix), dtype=torch.float64, device=a.device)
+    o2, _ = _as2d(out)
+    check(lib().sht_synth(grid._h, int(lmax), nm, _dev_f64(a, "alm"), a.stride(0),
+                          _dev_f64(o2, "out"), o2.stride(0), _stream(a.device)))
+    return out[0] if (sq and out.dim() == 2) else out
+
+
+def sht_adjoint(grid, lmax, maps, out=None):
+    """Y^T maps (adjoint synthesis, Sect. 3.2)."""
+    m, sq = _as2d(maps)
+    if m.shape[1] != grid.npix:
+        raise ValueError("map has the wrong number of pixels")
+    nm = m.shape[0]
+    if out is None:
+        out = torch.empty((nm, nalm(lmax)), dtype=torch.float64, device=m.device)
+    o2, _ = _as2d(out)
+    check(lib().sht_adjoint(grid._h, int(lmax), nm, _dev_f64(m, "maps"), m.stride(0),
+                            _dev_f64(o2, "out"), o2.stride(0), _stream(m.device)))
+    return out[0] if (sq and out.dim() == 2) else out
+
+
+class Model:
+    """Model handle: bands (grid, L_nu, beam, tau, q row) and components
+    (L_k, C_k^-1).  ``diag`` also builds the M_diag blocks."""
+
+    def __init__(self, bands, comps, q, diag=True):
+        self.grids = [b["grid"] for b in bands]
+        self.ncomp = len(comps)
+        self.nbands = len(bands)
+        self.lmax_comp = [int(c["lmax"]) for c in comps]
+        self.band_lmax = [int(b["lmax"]) for b in bands]
+        q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(self.nbands, self.ncomp))
+        keep = []
+        bd = (_lib.BandDesc * self.nbands)()
+        for i, b in enumerate(bands):
+            beam, pb = _host_f64(b["beam"])
+            tau, pt = _host_f64(b["tau"])
+            qr, pq = _host_f64(q[i])
+            if len(tau) != b["grid"].npix:
+                raise ValueError("tau has the wrong length")
+            if len(beam) < b["lmax"] + 1:
+                raise ValueError("beam shorter than lmax + 1")
+            keep += [beam, tau, qr]
+            bd[i] = _lib.BandDesc(b["grid"]._h, int(b["lmax"]), pb, pt, pq)
+        lk = (ctypes.c_int * self.ncomp)(*self.lmax_comp)
+        icl = (c_double_p * self.ncomp)()
+        for k, c in enumerate(comps):
+            a, p = _host_f64(c["invcl"])
+            if len(a) < c["lmax"] + 1:
+                raise ValueError("invcl shorter than lmax + 1")
+            keep.append(a)
+            icl[k] = p
+        desc = _lib.ModelDesc(self.ncomp, lk, icl, self.nbands, bd, 1 if diag else 0)
+        h = ctypes.c_void_p()
+        check(lib().crs_model_create(ctypes.byref(desc), _stream(), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        check(lib().crs_model_size(self._h, ctypes.byref(n)))
+        self.n = n.value
+        self.has_diag = bool(diag)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().crs_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alpha2(self):
+        a = np.empty(self.nbands)
+        check(lib().crs_model_alpha2(self._h, a.ctypes.data_as(c_double_p)))
+        return a
+
+    def set_mixing(self, q):
+        q, p = _host_f64(np.asarray(q, dtype=np.float64).reshape(self.nbands, self.ncomp))
+        check(lib().crs_model_set_mixing(self._h, p, _stream()))
+
+    def _vec(self, x, name):
+        x2, sq = _as2d(x)
+        if x2.shape[1] != self.n:
+            raise ValueError(f"{name} must have n = {self.n} entries per right-hand side")
+        return x2, sq
+
+    def _op(self, fn, x, name):
+        x2, sq = self._vec(x, name)
+        y = torch.empty_like(x2)
+        check(fn(self._h, x2.shape[0], _dev_f64(x2, name), _dev_f64(y, "out"), _stream(x2.device)))
+        return y[0] if sq else y
+
+    def apply_A(self, x):
+        return self._op(lib().apply_A, x, "x")
+
+    def apply_pinv(self, r):
+        return self._op(lib().apply_pinv_precond, r, "r")
+
+    def apply_diag(self, r):
+        return self._op(lib().apply_diag_precond, r, "r")
+
+    def pcg(self, b, precond="pinv", rtol=1e-8, maxiter=1000, x0=None, history=False,
+            raise_on_error=True):
+        b2, sq = self._vec(b, "b")
+        nrhs = b2.shape[0]
+        x = torch.zeros_like(b2) if x0 is None else self._vec(x0, "x0")[0].clone()
+        iters = (ctypes.c_int * nrhs)()
+        rel = (ctypes.c_double * nrhs)()
+        hist = np.zeros((max(1, maxiter), nrhs)) if history else None
+        hp = hist.ctypes.data_as(c_double_p) if history else None
+        st = lib().pcg_solve(self._h, _lib.PRECOND[precond], nrhs, _dev_f64(b2, "b"),
+                             _dev_f64(x, "x"), float(rtol), int(maxiter), iters, rel, hp,
+                             _stream(b2.device))
+        if raise_on_error:
+            check(st)
+        info = {"status": st, "iters": list(iters), "relres": list(rel)}
+        if history:
+            info["history"] = hist[:max(info["iters"] + [0])]
+        return (x[0] if sq else x), info
+
+    def build_rhs(self, d=None, omega1=None, omega2=None, nrhs=1):
+        dev = torch.device("cuda")
+        keep = []
+
+        def ptrs(lst):
+            if lst is None:
+                return None
+            arr = (ctypes.c_void_p * self.nbands)()
+            for i, t in enumerate(lst):
+                if t is None:
+                    arr[i] = None
+                else:
+                    t = t.contiguous()
+                    keep.append(t)
+                    arr[i] = _dev_f64(t, "map")
+            return arr
+
+        b = torch.empty((nrhs, self.n), dtype=torch.float64, device=dev)
+        w2 = None
+        if omega2 is not None:
+            w2t = omega2.contiguous()
+            keep.append(w2t)
+            w2 = _dev_f64(w2t, "omega2")
+        check(lib().build_rhs(self._h, nrhs, ptrs(d), ptrs(omega1), w2, _dev_f64(b, "b"),
+                              _stream(dev)))
+        return b
+
+    def project(self, x):
+        """P_nu x for every band: list of [nrhs, npix_nu] tensors."""
+        x2, sq = self._vec(x, "x")
+        nrhs = x2.shape[0]
+        outs = [torch.empty((nrhs, g.npix), dtype=torch.float64, device=x2.device)
+                for g in self.grids]
+        arr = (ctypes.c_void_p * self.nbands)(*[o.data_ptr() for o in outs])
+        check(lib().crs_model_project(self._h, nrhs, _dev_f64(x2, "x"), arr, _stream(x2.device)))
+        return [o[0] for o in outs] if sq else outs
+
+    def constrained_realization(self, d, seed, mode="cr", precond="pinv", rtol=1e-8,
+                                maxiter=1000, nrhs=1, raise_on_error=True):
+        dev = torch.device("cuda")
+        keep = []
+        arr = None
+        if d is not None:
+            arr = (ctypes.c_void_p * self.nbands)()
+            for i, t in enumerate(d):
+                t = t.contiguous()
+                keep.append(t)
+                arr[i] = _dev_f64(t, "d")
+        x = torch.empty((nrhs, self.n), dtype=torch.float64, device=dev)
+        iters = (ctypes.c_int * nrhs)()
+        rel = (ctypes.c_double * nrhs)()
+        st = lib().constrained_realization(self._h, nrhs, arr, ctypes.c_uint64(seed), _lib.MODE[mode],
+                                           _lib.PRECOND[precond], float(rtol), int(maxiter),
+                                           _dev_f64(x, "x"), iters, rel, _stream(dev))
+        if raise_on_error:
+            check(st)
+        return x, {"status": st, "iters": list(iters), "relres": list(rel)}
+
+
+def philox_normals(seed, stream, rhs, n, device="cuda"):
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    check(lib().crs_philox_normals(ctypes.c_uint64(seed), ctypes.c_uint64(stream),
+                                   ctypes.c_uint64(rhs), int(n), _dev_f64(out, "out"),
+                                   _stream(out.device)))
+    return out
+
+
+def set_profiling(on):
+    check(lib().crs_set_profiling(1 if on else 0))
+
+
+def kernel_stats(family):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    w = ctypes.c_double()
+    check(lib().crs_kernel_stats(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
+    return {"launches": n.value, "ms": ms.value, "work": w.value}
+
+
+def kernel_stats_reset():
+    check(lib().crs_kernel_stats_reset())
+
+
+def model_from_problem(problem, taus, grids=None, diag=True):
+    """Library model for a recipe from ``inputs`` with given tau maps."""
+    from . import inputs
+    if grids is None:
+        cache = {}
+        grids = []
+        for b in problem["bands"]:
+            if b["grid"] not in cache:
+                cache[b["grid"]] = Grid.from_spec(b["grid"])
+            grids.append(cache[b["grid"]])
+    beams = inputs.beams(problem)
+    bands = [{"grid": g, "lmax": b["lmax"], "beam": bm, "tau": t}
+             for g, b, bm, t in zip(grids, problem["bands"], beams, taus)]
+    comps = [{"lmax": c["lmax"], "invcl": icl}
+             for c, icl in zip(problem["comps"], inputs.priors(problem))]
+    return Model(bands, comps, problem["q"], diag=diag)

@@ -1,0 +1,241 @@
+// Error handling, profiling hooks and the public transform entry points.
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace crs {
+
+namespace {
+thread_local int g_last_code = CRS_OK;
+thread_local std::string g_last_msg;
+
+struct ProfRecord {
+  int family;
+  double work;
+  hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pending;
+struct ProfTotals {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double work = 0.0;
+};
+ProfTotals g_prof_totals[FAM_COUNT];
+
+void prof_resolve_locked() {
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      g_prof_totals[r.family].launches += 1;
+      g_prof_totals[r.family].ms += ms;
+      g_prof_totals[r.family].work += r.work;
+    }
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  g_prof_pending.clear();
+}
+}  // namespace
+
+void set_error(int code, const std::string& msg) {
+  g_last_code = code;
+  g_last_msg = msg;
+}
+
+int fail(int code, const std::string& msg) {
+  set_error(code, msg);
+  return code;
+}
+
+ProfScope::ProfScope(int fam, double w, hipStream_t st) : family(fam), work(w), s(st) {
+  if (!g_prof_on) return;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    e0 = e1 = nullptr;
+    return;
+  }
+  (void)hipEventRecord(e0, s);
+}
+
+ProfScope::~ProfScope() {
+  if (!e0) return;
+  (void)hipEventRecord(e1, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back({family, work, e0, e1});
+  if (g_prof_pending.size() > 4096) prof_resolve_locked();
+}
+
+static void check_maps(int lmax, int nmaps, int64_t as, int64_t ms_, int64_t npix) {
+  CRS_CHECK(lmax >= 0, CRS_EINVAL, "lmax must be >= 0");
+  CRS_CHECK(nmaps >= 1, CRS_EINVAL, "nmaps must be >= 1");
+  CRS_CHECK(as >= (int64_t)(lmax + 1) * (lmax + 1), CRS_EINVAL, "alm_stride shorter than (lmax+1)^2");
+  CRS_CHECK(ms_ >= npix, CRS_EINVAL, "map_stride shorter than npix");
+}
+
+LegArgs leg_args(crs_grid g, ShtPlan& p) {
+  LegArgs a;
+  a.g = p.g.p;
+  a.ls = p.ls.p;
+  a.ms = p.ms.p;
+  a.zpair = g->d_zpair.p;
+  a.lmax = p.lmax;
+  a.npairs = p.npairs;
+  a.nring = g->nring;
+  return a;
+}
+
+RingArgs ring_args(crs_grid g, int lmax) {
+  RingArgs r;
+  r.nphi = g->d_nphi.p;
+  r.offset = g->d_offset.p;
+  r.phinum = g->d_phinum.p;
+  r.phiden = g->d_phiden.p;
+  r.nfac = g->d_nfac.p;
+  r.fac = g->d_fac.p;
+  r.twoff = g->d_twoff.p;
+  r.tw = g->d_tw.p;
+  r.nring = g->nring;
+  r.lmax = lmax;
+  return r;
+}
+
+double leg_flops(const ShtPlan& p, int nmaps) {
+  // per evaluated (ring pair, l, m): 4 flops of recurrence shared by the
+  // maps + 4 flops (cos and sin FMAs) per map
+  return (double)p.eff_triples * (4.0 + 4.0 * nmaps);
+}
+
+double ring_bytes(crs_grid g, int lmax, int nmaps, int mode) {
+  // algorithmic HBM traffic: phase rows (16 B per m) read and/or written,
+  // map pixels read or written, weights read
+  double ph = (double)g->nring * (lmax + 1) * 16.0;
+  double px = (double)g->npix * 8.0;
+  switch (mode) {
+    case RING_SYNTH: return nmaps * (ph + px);
+    case RING_ADJOINT: return nmaps * (px + ph);
+    case RING_ROUNDTRIP: return nmaps * (2.0 * ph + px);
+    default: return nmaps * (px + ph);
+  }
+}
+
+}  // namespace crs
+
+using namespace crs;
+
+extern "C" {
+
+const char* crs_strerror(int status) {
+  switch (status) {
+    case CRS_OK: return "ok";
+    case CRS_EINVAL: return "invalid argument";
+    case CRS_ENOMEM: return "out of memory";
+    case CRS_EHIP: return "HIP runtime error";
+    case CRS_ENOTCONV: return "PCG did not converge within maxiter";
+    case CRS_EBREAKDOWN: return "PCG breakdown";
+    case CRS_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int crs_last_error(char* buf, size_t n) {
+  if (buf && n) {
+    std::strncpy(buf, g_last_msg.c_str(), n - 1);
+    buf[n - 1] = 0;
+  }
+  return g_last_code;
+}
+
+const char* crs_version(void) { return "crsolve 0.1 (gfx950, float64)"; }
+
+int crs_set_profiling(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return CRS_OK;
+}
+
+int crs_kernel_stats(const char* family, int64_t* launches, double* total_ms, double* total_work) {
+  return guarded([&] {
+    CRS_CHECK(family != nullptr, CRS_EINVAL, "family is NULL");
+    int f = -1;
+    if (!std::strcmp(family, "legendre_synth")) f = FAM_LEG_SYNTH;
+    if (!std::strcmp(family, "legendre_adjoint")) f = FAM_LEG_ADJ;
+    if (!std::strcmp(family, "ring_fft")) f = FAM_RING;
+    CRS_CHECK(f >= 0, CRS_EINVAL, "unknown kernel family");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_resolve_locked();
+    if (launches) *launches = g_prof_totals[f].launches;
+    if (total_ms) *total_ms = g_prof_totals[f].ms;
+    if (total_work) *total_work = g_prof_totals[f].work;
+    return CRS_OK;
+  });
+}
+
+int crs_kernel_stats_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_resolve_locked();
+  for (auto& t : g_prof_totals) t = ProfTotals{};
+  return CRS_OK;
+}
+
+int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_stride, double* map,
+              int64_t map_stride, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(alm != nullptr && map != nullptr, CRS_EINVAL, "alm or map is NULL");
+    check_maps(lmax, nmaps, alm_stride, map_stride, g->npix);
+    hipStream_t s = (hipStream_t)st;
+    ShtPlan& p = get_plan(g, lmax, s);
+    if (!g->work) g->work = std::make_unique<GridWork>();
+    GridWork& w = *g->work;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
+    const int64_t pst = (int64_t)g->nring * (lmax + 1);
+    w.uhat.alloc((size_t)nmaps * nalm);
+    w.phase.alloc((size_t)nmaps * pst);
+    launch_hat_scale(p.f.p, lmax, nmaps, alm, alm_stride, 1, 0, w.uhat.p, nalm, false, s);
+    {
+      ProfScope ps(FAM_LEG_SYNTH, leg_flops(p, nmaps), s);
+      launch_leg_synth(leg_args(g, p), nmaps, w.uhat.p, nalm, w.phase.p, pst, s);
+    }
+    {
+      ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_SYNTH), s);
+      launch_ring(ring_args(g, lmax), RING_SYNTH, nmaps, w.phase.p, pst, nullptr, map, map_stride,
+                  nullptr, 1, s);
+    }
+    return CRS_OK;
+  });
+}
+
+int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride, double* alm,
+                int64_t alm_stride, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(alm != nullptr && map != nullptr, CRS_EINVAL, "alm or map is NULL");
+    check_maps(lmax, nmaps, alm_stride, map_stride, g->npix);
+    hipStream_t s = (hipStream_t)st;
+    ShtPlan& p = get_plan(g, lmax, s);
+    if (!g->work) g->work = std::make_unique<GridWork>();
+    GridWork& w = *g->work;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
+    const int64_t pst = (int64_t)g->nring * (lmax + 1);
+    const int ntiles = leg_adjoint_tiles(p.npairs);
+    w.phase.alloc((size_t)nmaps * pst);
+    w.vpart.alloc((size_t)ntiles * nmaps * nalm);
+    {
+      ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_ADJOINT), s);
+      launch_ring(ring_args(g, lmax), RING_ADJOINT, nmaps, w.phase.p, pst, map, nullptr, map_stride,
+                  nullptr, 1, s);
+    }
+    {
+      ProfScope ps(FAM_LEG_ADJ, leg_flops(p, nmaps), s);
+      launch_leg_adjoint(leg_args(g, p), nmaps, w.phase.p, pst, w.vpart.p, nalm,
+                         (int64_t)nmaps * nalm, false, s);
+    }
+    launch_hat_scale(p.f.p, lmax, nmaps, w.vpart.p, nalm, ntiles, (int64_t)nmaps * nalm, alm,
+                     alm_stride, false, s);
+    return CRS_OK;
+  });
+}
+
+}  // extern "C"

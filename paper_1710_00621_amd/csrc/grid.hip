@@ -1,0 +1,432 @@
+// Ring grids (HEALPix RING, Gauss-Legendre), per-ring FFT tables and the
+// per-(grid, lmax) Legendre plans.
+//
+// HEALPix RING geometry follows Gorski et al. (2005); the paper uses HEALPix
+// sky maps and recommends Gauss-Legendre grids where exact quadrature is
+// wanted (Sect. 2.1, Sect. 2.2 below eq:Q).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace crs {
+
+namespace {
+
+// sin(pi x), cos(pi x) with exact argument reduction (x a ratio of integers
+// reduced modulo 2 by the caller); accurate to a few ulps.
+void host_sincospi(double x, double* s, double* c) {
+  x = std::fmod(x, 2.0);
+  if (x < 0) x += 2.0;
+  // reduce to [0, 0.5] using symmetries
+  double sign_s = 1.0, sign_c = 1.0;
+  if (x >= 1.0) { x -= 1.0; sign_s = -1.0; sign_c = -1.0; }
+  if (x > 0.5) { x = 1.0 - x; sign_c = -sign_c; }
+  double ss, cc;
+  if (x <= 0.25) {
+    ss = std::sin(M_PI * x);
+    cc = std::cos(M_PI * x);
+  } else {
+    double y = 0.5 - x;
+    ss = std::cos(M_PI * y);
+    cc = std::sin(M_PI * y);
+  }
+  *s = sign_s * ss;
+  *c = sign_c * cc;
+}
+
+std::vector<int> factorize(int n) {
+  std::vector<int> f;
+  while (n % 4 == 0) { f.push_back(4); n /= 4; }
+  while (n % 2 == 0) { f.push_back(2); n /= 2; }
+  for (int p = 3; p * p <= n; p += 2)
+    while (n % p == 0) { f.push_back(p); n /= p; }
+  if (n > 1) f.push_back(n);
+  if (f.empty()) f.push_back(1);
+  return f;
+}
+
+// Gauss-Legendre nodes (descending) via Newton iteration on theta.
+void gl_nodes(int n, std::vector<double>& z, std::vector<double>& st, std::vector<double>& w) {
+  z.resize(n);
+  st.resize(n);
+  w.resize(n);
+  for (int k = 0; k < n; ++k) {
+    double th = M_PI * (k + 0.75) / (n + 0.5);
+    double x = 0, pn = 0, pn1 = 0;
+    for (int it = 0; it < 100; ++it) {
+      x = std::cos(th);
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      pn = (n == 1) ? x : p1;
+      pn1 = (n == 1) ? 1.0 : p0;
+      // dP_n/dx = n (x P_n - P_{n-1}) / (x^2 - 1); d/dtheta = -sin * dP/dx
+      double s = std::sin(th);
+      double dpdx = n * (x * pn - pn1) / (x * x - 1.0);
+      double dth = pn / (-s * dpdx);
+      th -= dth;
+      if (std::fabs(dth) < 1e-16) break;
+    }
+    x = std::cos(th);
+    double s = std::sin(th);
+    // P_{n-1}(x) at the converged node
+    double p0 = 1.0, p1 = x;
+    if (n == 1) p1 = 1.0;
+    else {
+      for (int j = 2; j <= n - 1; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 2) p1 = x;
+    }
+    double pm1 = (n == 1) ? 1.0 : p1;
+    z[k] = x;
+    st[k] = s;
+    w[k] = 2.0 * s * s / ((n * pm1) * (n * pm1));
+  }
+}
+
+}  // namespace
+
+// Uploads per-ring tables (lengths, offsets, phi0, FFT factors, twiddles).
+void grid_finalize(crs_grid g, hipStream_t s) {
+  int nr = g->nring;
+  g->offset.resize(nr);
+  int64_t off = 0;
+  for (int r = 0; r < nr; ++r) {
+    g->offset[r] = off;
+    off += g->nphi[r];
+  }
+  g->npix = off;
+  for (int r = 0; r < nr; ++r)
+    CRS_CHECK(g->nphi[r] <= kMaxRing, CRS_EUNSUPPORTED,
+              "ring length above 4096 pixels is not supported");
+  // factors and twiddle tables (T_{2N}[t] = exp(-2 pi i t / (2N)), t < 2N)
+  std::vector<int> nfac(nr), fac((size_t)nr * kMaxFactors, 1);
+  std::vector<int64_t> twoff(nr);
+  std::map<int, int64_t> tw_of;
+  std::vector<double2> tw;
+  for (int r = 0; r < nr; ++r) {
+    int n = g->nphi[r];
+    auto f = factorize(n);
+    CRS_CHECK((int)f.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
+    nfac[r] = (int)f.size();
+    for (size_t i = 0; i < f.size(); ++i) fac[(size_t)r * kMaxFactors + i] = f[i];
+    auto it = tw_of.find(n);
+    if (it == tw_of.end()) {
+      int64_t o = (int64_t)tw.size();
+      tw_of[n] = o;
+      for (int t = 0; t < 2 * n; ++t) {
+        double sv, cv;
+        host_sincospi((double)t / (double)n, &sv, &cv);
+        tw.push_back(make_double2(cv, -sv));
+      }
+      twoff[r] = o;
+    } else {
+      twoff[r] = it->second;
+    }
+  }
+  int np = (nr + 1) / 2;
+  std::vector<double> zp(np), sp(np);
+  for (int p = 0; p < np; ++p) {
+    zp[p] = g->z[p];
+    sp[p] = g->sint[p];
+  }
+  g->d_nphi.upload(g->nphi, s);
+  g->d_offset.upload(g->offset, s);
+  g->d_phinum.upload(g->phi0_num, s);
+  g->d_phiden.upload(g->phi0_den, s);
+  g->d_nfac.upload(nfac, s);
+  g->d_fac.upload(fac, s);
+  g->d_twoff.upload(twoff, s);
+  g->d_tw.upload(tw, s);
+  g->d_zpair.upload(zp, s);
+  g->d_spair.upload(sp, s);
+  CRS_HIP(hipStreamSynchronize(s));
+}
+
+void build_healpix(crs_grid g, int nside) {
+  g->kind = 0;
+  g->nside = nside;
+  int nr = 4 * nside - 1;
+  g->nring = nr;
+  g->z.resize(nr);
+  g->sint.resize(nr);
+  g->nphi.resize(nr);
+  g->phi0_num.resize(nr);
+  g->phi0_den.resize(nr);
+  g->ringw.assign(nr, 4.0 * M_PI / (12.0 * nside * (double)nside));
+  double ns = nside;
+  for (int k = 0; k < nr; ++k) {
+    int i = k + 1;
+    if (i < nside || i > 3 * nside) {
+      int ii = (i < nside) ? i : 4 * nside - i;
+      double om = (double)ii * ii / (3.0 * ns * ns);  // 1 - |z|
+      double zz = 1.0 - om;
+      g->z[k] = (i < nside) ? zz : -zz;
+      g->sint[k] = std::sqrt(om * (2.0 - om));
+      g->nphi[k] = 4 * ii;
+      g->phi0_num[k] = 1;   // phi0 = pi / (4 ii) = pi / nphi
+      g->phi0_den[k] = 4 * ii;
+    } else {
+      double zz = 4.0 / 3.0 - (2.0 * i) / (3.0 * ns);
+      g->z[k] = zz;
+      g->sint[k] = std::sqrt((1.0 - zz) * (1.0 + zz));
+      g->nphi[k] = 4 * nside;
+      bool shifted = ((i - nside) % 2) == 0;
+      g->phi0_num[k] = shifted ? 1 : 0;
+      g->phi0_den[k] = 4 * nside;
+    }
+  }
+}
+
+void build_gl(crs_grid g, int nrings, int nphi) {
+  g->kind = 1;
+  g->nring = nrings;
+  g->nphi_gl = nphi;
+  std::vector<double> w;
+  gl_nodes(nrings, g->z, g->sint, w);
+  g->nphi.assign(nrings, nphi);
+  g->phi0_num.assign(nrings, 0);
+  g->phi0_den.assign(nrings, nphi);
+  g->ringw.resize(nrings);
+  for (int r = 0; r < nrings; ++r) g->ringw[r] = w[r] * 2.0 * M_PI / nphi;
+}
+
+// ----------------------------------------------------------- Legendre plan
+// mu-recurrence tables.  With a_lm = sqrt((4l^2-1)/(l^2-m^2)),
+// b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)) and c_lm = a_lm b_lm the normalised
+// associated Legendre functions obey lambda_l = a_l z lambda_{l-1} - c_l lambda_{l-2}.
+// Writing lambda_l = f_l mu_l with f_m = f_{m+1} = 1, f_l = c_l f_{l-2} turns
+// this into mu_l = g_l z mu_{l-1} - mu_{l-2}, g_l = a_l f_{l-1} / f_l: one
+// multiply and one FMA per step.  Triangle layout: entry (l, m) at
+// tri(m) + l - m, tri(m) = m (L+1) - m (m-1) / 2.
+__host__ __device__ static inline int64_t tri_off(int L, int m) { return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2; }
+
+__global__ void k_start_table(const double* __restrict__ gtab, const double* __restrict__ ftab,
+                              const double* __restrict__ zp, const double* __restrict__ sp,
+                              const double* __restrict__ pm_mant, const int* __restrict__ pm_exp,
+                              int L, int npairs, double thr, int* __restrict__ ls_out,
+                              double2* __restrict__ ms_out) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = blockIdx.y;
+  if (p >= npairs || m > L) return;
+  double z = zp[p], s = sp[p];
+  // lambda_mm = P_m sin^m(theta), carried as mantissa * 2^e
+  double mant = pm_mant[m];
+  long e = pm_exp[m];
+  if (m > 0) {
+    if (s == 0.0) {
+      mant = 0.0;
+    } else {
+      int se;
+      double sm = frexp(s, &se);
+      double r = 1.0;
+      long er = 0;
+      double base = sm;
+      long eb = se;
+      int k = m;
+      while (k) {
+        if (k & 1) {
+          int t;
+          r = frexp(r * base, &t);
+          er += eb + t;
+        }
+        k >>= 1;
+        if (k) {
+          int t;
+          base = frexp(base * base, &t);
+          eb = 2 * eb + t;
+        }
+      }
+      int t;
+      mant = frexp(mant * r, &t);
+      e += er + t;
+    }
+  }
+  const double* g = gtab + tri_off(L, m) - m;
+  const double* f = ftab + tri_off(L, m) - m;
+  double mu_prev = 0.0, mu_cur = mant;
+  int l = m;
+  int lsv = L + 1;
+  double2 msv = make_double2(0.0, 0.0);
+  // threshold test on |lambda_l| = f_l |mu_l| 2^e
+  while (true) {
+    double v = fabs(f[l] * mu_cur);
+    if (v != 0.0 && e > -2000 && ldexp(v, (int)e) >= thr) {
+      lsv = l;
+      msv = make_double2(ldexp(mu_prev, (int)e), ldexp(mu_cur, (int)e));
+      break;
+    }
+    ++l;
+    if (l > L) break;
+    double nx = g[l] * z * mu_cur - mu_prev;
+    mu_prev = mu_cur;
+    mu_cur = nx;
+    if (fabs(mu_cur) > 0x1p600) {
+      mu_cur *= 0x1p-600;
+      mu_prev *= 0x1p-600;
+      e += 600;
+    }
+  }
+  ls_out[(size_t)m * npairs + p] = lsv;
+  ms_out[(size_t)m * npairs + p] = msv;
+}
+
+constexpr double kSkipThreshold = 0x1p-100;  // |lambda| below this is not evaluated
+
+ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s) {
+  auto it = g->plans.find(lmax);
+  if (it != g->plans.end()) return *it->second;
+  auto plan = std::make_unique<ShtPlan>();
+  int L = lmax;
+  plan->lmax = L;
+  plan->npairs = (g->nring + 1) / 2;
+  int64_t ntri = (int64_t)(L + 1) * (L + 2) / 2;
+  std::vector<double> gt(ntri, 0.0), ft(ntri, 0.0);
+  for (int m = 0; m <= L; ++m) {
+    int64_t o = tri_off(L, m) - m;
+    ft[o + m] = 1.0;
+    if (m + 1 <= L) {
+      ft[o + m + 1] = 1.0;
+      gt[o + m + 1] = std::sqrt(2.0 * m + 3.0);
+    }
+    for (int l = m + 2; l <= L; ++l) {
+      double dl = l, dm = m;
+      double a = std::sqrt((4.0 * dl * dl - 1.0) / ((dl - dm) * (dl + dm)));
+      double b = std::sqrt(((dl - 1.0 - dm) * (dl - 1.0 + dm)) / (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
+      ft[o + l] = a * b * ft[o + l - 2];
+      gt[o + l] = a * ft[o + l - 1] / ft[o + l];
+    }
+  }
+  // P_m = lambda_00 prod_{k<=m} sqrt((2k+1)/(2k)) as mantissa/exponent
+  std::vector<double> pmm(L + 1);
+  std::vector<int> pme(L + 1);
+  {
+    int e;
+    double mant = std::frexp(1.0 / std::sqrt(4.0 * M_PI), &e);
+    long ee = e;
+    pmm[0] = mant;
+    pme[0] = (int)ee;
+    for (int m = 1; m <= L; ++m) {
+      mant *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+      int t;
+      mant = std::frexp(mant, &t);
+      ee += t;
+      pmm[m] = mant;
+      pme[m] = (int)ee;
+    }
+  }
+  plan->g.upload(gt, s);
+  plan->f.upload(ft, s);
+  DevBuf<double> dpm;
+  DevBuf<int> dpe;
+  dpm.upload(pmm, s);
+  dpe.upload(pme, s);
+  plan->ls.alloc((size_t)(L + 1) * plan->npairs);
+  plan->ms.alloc((size_t)(L + 1) * plan->npairs);
+  dim3 grid((plan->npairs + 127) / 128, L + 1);
+  hipLaunchKernelGGL(k_start_table, grid, dim3(128), 0, s, plan->g.p, plan->f.p, g->d_zpair.p,
+                     g->d_spair.p, dpm.p, dpe.p, L, plan->npairs, kSkipThreshold, plan->ls.p,
+                     plan->ms.p);
+  CRS_HIP(hipGetLastError());
+  std::vector<int> lsh((size_t)(L + 1) * plan->npairs);
+  CRS_HIP(hipMemcpyAsync(lsh.data(), plan->ls.p, lsh.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipStreamSynchronize(s));
+  int64_t eff = 0;
+  for (int m = 0; m <= L; ++m)
+    for (int p = 0; p < plan->npairs; ++p) {
+      int v = lsh[(size_t)m * plan->npairs + p];
+      if (v <= L) eff += L - v + 1;
+    }
+  plan->eff_triples = eff;
+  plan->nominal_triples = (int64_t)plan->npairs * ntri;
+  auto& ref = *plan;
+  g->plans[lmax] = std::move(plan);
+  return ref;
+}
+
+}  // namespace crs
+
+using namespace crs;
+
+extern "C" {
+
+int crs_grid_healpix(int nside, crs_grid* out) {
+  return guarded([&] {
+    CRS_CHECK(out != nullptr, CRS_EINVAL, "out is NULL");
+    CRS_CHECK(nside >= 1, CRS_EINVAL, "nside must be >= 1");
+    CRS_CHECK(nside <= 1024, CRS_EUNSUPPORTED, "nside above 1024 is not supported");
+    auto g = std::make_unique<crs_grid_s>();
+    CRS_HIP(hipGetDevice(&g->device));
+    build_healpix(g.get(), nside);
+    grid_finalize(g.get(), nullptr);
+    *out = g.release();
+    return CRS_OK;
+  });
+}
+
+int crs_grid_gauss_legendre(int nrings, int nphi, crs_grid* out) {
+  return guarded([&] {
+    CRS_CHECK(out != nullptr, CRS_EINVAL, "out is NULL");
+    CRS_CHECK(nrings >= 1 && nphi >= 1, CRS_EINVAL, "nrings and nphi must be >= 1");
+    CRS_CHECK(nphi <= kMaxRing, CRS_EUNSUPPORTED, "nphi above 4096 is not supported");
+    auto g = std::make_unique<crs_grid_s>();
+    CRS_HIP(hipGetDevice(&g->device));
+    build_gl(g.get(), nrings, nphi);
+    grid_finalize(g.get(), nullptr);
+    *out = g.release();
+    return CRS_OK;
+  });
+}
+
+int crs_grid_info(crs_grid g, int* nrings, int64_t* npix) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    if (nrings) *nrings = g->nring;
+    if (npix) *npix = g->npix;
+    return CRS_OK;
+  });
+}
+
+int crs_grid_pixel_centres(crs_grid g, double* z, double* phi) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(z != nullptr && phi != nullptr, CRS_EINVAL, "z or phi is NULL");
+    for (int r = 0; r < g->nring; ++r) {
+      int n = g->nphi[r];
+      for (int j = 0; j < n; ++j) {
+        z[g->offset[r] + j] = g->z[r];
+        // phi = pi * (num/den + 2 j / n)
+        double x = (double)g->phi0_num[r] / g->phi0_den[r] + 2.0 * j / n;
+        phi[g->offset[r] + j] = M_PI * x;
+      }
+    }
+    return CRS_OK;
+  });
+}
+
+int crs_grid_weights(crs_grid g, double* w) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(w != nullptr, CRS_EINVAL, "w is NULL");
+    for (int r = 0; r < g->nring; ++r)
+      for (int j = 0; j < g->nphi[r]; ++j) w[g->offset[r] + j] = g->ringw[r];
+    return CRS_OK;
+  });
+}
+
+int crs_grid_destroy(crs_grid g) {
+  return guarded([&] {
+    delete g;
+    return CRS_OK;
+  });
+}
+
+}  // extern "C"

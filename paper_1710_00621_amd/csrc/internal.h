@@ -1,0 +1,196 @@
+// Internal declarations of the crsolve HIP library (gfx950, float64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/crsolve.h"
+
+namespace crs {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(int code, const std::string& msg);
+int fail(int code, const std::string& msg);  // sets and returns code
+
+#define CRS_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::crs::Error{CRS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define CRS_CHECK(cond, code, msg)                          \
+  do {                                                      \
+    if (!(cond)) throw ::crs::Error{(code), (msg)};         \
+  } while (0)
+
+// Runs f() and turns exceptions into status codes.
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(CRS_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(CRS_EINVAL, e.what());
+  }
+}
+
+// Device buffer owned by a handle.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{CRS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void upload(const T* host, size_t count, hipStream_t s) {
+    alloc(count);
+    if (count) CRS_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
+};
+
+constexpr int kMaxRing = 4096;   // ring FFT length limit (LDS resident)
+constexpr int kMaxFactors = 16;  // radices per ring length
+
+// ---------------------------------------------------------------- grids
+// Per-(grid, lmax) Legendre plan: start table and recurrence tables.
+struct ShtPlan {
+  int lmax = 0;
+  int npairs = 0;
+  int64_t eff_triples = 0;     // (ring pair, l, m) triples the kernels evaluate
+  int64_t nominal_triples = 0; // npairs * (L+1)(L+2)/2
+  DevBuf<double> g;            // triangle: g_lm, mu recurrence coefficient
+  DevBuf<double> f;            // triangle: f_lm, lambda = f * mu
+  DevBuf<int> ls;              // [L+1][npairs]: first l evaluated (L+1 = never)
+  DevBuf<double2> ms;          // [L+1][npairs]: (mu_{ls-1}, mu_ls)
+  std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
+};
+
+// Workspace of the public transforms (sht_synth / sht_adjoint).
+struct GridWork {
+  DevBuf<double> uhat;
+  DevBuf<double2> phase;
+  DevBuf<double> vpart;
+};
+
+}  // namespace crs
+
+struct crs_grid_s {
+  int kind = 0;  // 0 HEALPix, 1 Gauss-Legendre
+  int nside = 0, nring = 0, nphi_gl = 0;
+  int64_t npix = 0;
+  std::vector<double> z, sint, ringw;
+  std::vector<int> nphi, phi0_num, phi0_den;  // phi0 = pi * num / den
+  std::vector<int64_t> offset;
+  // device ring tables
+  crs::DevBuf<int> d_nphi, d_phinum, d_phiden, d_nfac, d_fac;
+  crs::DevBuf<int64_t> d_offset, d_twoff;
+  crs::DevBuf<double> d_zpair;    // z of the north ring of each pair
+  crs::DevBuf<double> d_spair;    // sin(theta) of the north ring of each pair
+  crs::DevBuf<double2> d_tw;      // twiddles exp(-2 pi i t / N) per distinct N
+  std::map<int, std::unique_ptr<crs::ShtPlan>> plans;
+  std::unique_ptr<crs::GridWork> work;
+  int device = 0;
+};
+
+namespace crs {
+
+ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s);
+
+// ------------------------------------------------------------ kernels API
+// Legendre stage.  Harmonic inputs are "hat" vectors: u^ = c_m f_lm u.
+struct LegArgs {
+  const double* g;        // triangle
+  const int* ls;          // [L+1][npairs]
+  const double2* ms;      // [L+1][npairs]
+  const double* zpair;    // [npairs]
+  int lmax, npairs, nring;
+};
+// phase: [nmaps][nring][L+1] double2 (cos, sin parts)
+void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
+                      double2* phase, int64_t pstride, hipStream_t s);
+// Adjoint: writes ntiles partial vectors vpart[tile][map][nalm]; returns ntiles.
+int leg_adjoint_tiles(int npairs);
+void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
+                        double* vpart, int64_t vstride, int64_t tstride, bool square,
+                        hipStream_t s);
+
+// Ring FFT stage.
+enum RingMode { RING_SYNTH = 0, RING_ADJOINT = 1, RING_ROUNDTRIP = 2, RING_DIAG = 3 };
+struct RingArgs {
+  const int* nphi;
+  const int64_t* offset;
+  const int* phinum;
+  const int* phiden;
+  const int* nfac;
+  const int* fac;
+  const int64_t* twoff;
+  const double2* tw;
+  int nring, lmax;
+};
+// maps j = 0..nmaps-1 use weight weights[j / maps_per_weight] (RING_ROUNDTRIP).
+void launch_ring(const RingArgs& a, RingMode mode, int nmaps, double2* phase, int64_t pstride,
+                 const double* map_in, double* map_out, int64_t mstride,
+                 const double* const* weights, int maps_per_weight, hipStream_t s);
+
+// Scaling between plain and hat vectors: out = c_m f_lm in (+ sum over tiles).
+void launch_hat_scale(const double* f, int lmax, int nmaps, const double* in, int64_t istride,
+                      int ntiles, int64_t tstride, double* out, int64_t ostride, bool square,
+                      hipStream_t s);
+
+// Profiling hooks (no-ops unless profiling is on).
+struct ProfScope {
+  int family;
+  double work;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(int fam, double w, hipStream_t st);
+  ~ProfScope();
+};
+enum { FAM_LEG_SYNTH = 0, FAM_LEG_ADJ = 1, FAM_RING = 2, FAM_COUNT = 3 };
+
+}  // namespace crs

@@ -1,0 +1,146 @@
+"""GPU parity of the spherical harmonic transforms against the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry, sht
+from oracle.legendre import LegendreSweep
+
+pytestmark = pytest.mark.gpu
+
+SHT_TOL = 1e-10  # relative (max-abs error over max-abs value), per SHT
+
+
+def _setup():
+    import torch
+    from paper_1710_00621_amd import crsolve
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, crsolve
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+CASES = [
+    (("gl", 33, 65), 32, 1),
+    (("gl", 6, 7), 9, 2),        # nphi < 2L+1: aliasing on every ring
+    (("healpix", 1), 3, 1),
+    (("healpix", 8), 16, 3),
+    (("healpix", 16), 40, 2),    # L > 2 Nside: polar rings alias
+    (("healpix", 32), 70, 1),    # ragged: 127 rings, 64 pairs, odd L
+    (("healpix", 64), 128, 9),   # several ring tiles, nmaps > 8
+    (("healpix", 13), 0, 1),     # lmax = 0, odd Nside (non power-of-two rings)
+]
+
+
+@pytest.mark.parametrize("spec,lmax,nmaps", CASES)
+def test_sht_synth_and_adjoint_match_oracle(spec, lmax, nmaps):
+    torch, crsolve = _setup()
+    print(f"case synth/adjoint {spec} lmax={lmax} nmaps={nmaps}", flush=True)
+    g = crsolve.Grid.from_spec(spec)
+    og = geometry.make_grid(spec)
+    assert g.npix == og.npix
+    rng = np.random.default_rng(7)
+    alm = rng.standard_normal((nmaps, sht.nalm(lmax)))
+    maps = rng.standard_normal((nmaps, og.npix))
+    ref_map = sht.synth(og, lmax, alm)
+    ref_alm = sht.adjoint(og, lmax, maps)
+    dev = torch.device("cuda")
+    got_map = crsolve.sht_synth(g, lmax, torch.tensor(alm, device=dev)).cpu().numpy()
+    got_alm = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
+    assert _rel(got_map, ref_map) < SHT_TOL
+    assert _rel(got_alm, ref_alm) < SHT_TOL
+
+
+def test_grid_geometry_matches_oracle():
+    torch, crsolve = _setup()
+    for spec in (("healpix", 1), ("healpix", 5), ("healpix", 64), ("gl", 33, 65), ("gl", 17, 40)):
+        g = crsolve.Grid.from_spec(spec)
+        og = geometry.make_grid(spec)
+        z, phi = g.pixel_centres()
+        oz, ophi = og.pixel_centres()
+        np.testing.assert_allclose(z, oz, atol=2e-16)
+        np.testing.assert_allclose(phi, ophi, atol=1e-14)
+        np.testing.assert_allclose(g.weights(), og.pixel_weights(), rtol=1e-12)
+
+
+def test_gl_round_trip_on_device():
+    """Y^T W Y = I on the 33 x 65 GL grid at L = 32 (Sect. 2.1)."""
+    torch, crsolve = _setup()
+    g = crsolve.Grid.gauss_legendre(33, 65)
+    w = torch.tensor(g.weights(), device="cuda")
+    a = torch.randn(4, sht.nalm(32), dtype=torch.float64, device="cuda")
+    back = crsolve.sht_adjoint(g, 32, crsolve.sht_synth(g, 32, a) * w)
+    assert float((back - a).abs().max()) < 1e-13
+
+
+def test_adjoint_identity_and_determinism():
+    torch, crsolve = _setup()
+    g = crsolve.Grid.healpix(32)
+    L = 96
+    x = torch.randn(2, sht.nalm(L), dtype=torch.float64, device="cuda")
+    y = torch.randn(2, g.npix, dtype=torch.float64, device="cuda")
+    yx = crsolve.sht_synth(g, L, x)
+    xty = crsolve.sht_adjoint(g, L, y)
+    lhs = (yx * y).sum(dim=1)
+    rhs = (x * xty).sum(dim=1)
+    assert float(((lhs - rhs).abs() / lhs.abs()).max()) < 1e-12
+    # bitwise determinism (fixed-order reductions)
+    assert torch.equal(crsolve.sht_adjoint(g, L, y), xty)
+    assert torch.equal(crsolve.sht_synth(g, L, x), yx)
+
+
+def _ring_subset(og, rings):
+    """Oracle grid restricted to some rings (for sampled checks at full size)."""
+    sub = geometry.Grid(og.kind, og.z[rings], og.sint[rings], og.nphi[rings], og.phi0[rings],
+                        og.ring_weight[rings], og.params)
+    return sub
+
+
+@pytest.mark.parametrize("nside,lmax", [(256, 512), (1024, 2000)])
+def test_sht_full_size_sampled(nside, lmax):
+    """At the large band shapes: synthesis checked on sampled rings (polar,
+    cap/belt boundary, equator) and the adjoint on sampled m, each computed
+    by the oracle one ring / one m at a time."""
+    torch, crsolve = _setup()
+    print(f"case full-size sampled nside={nside} lmax={lmax}", flush=True)
+    g = crsolve.Grid.healpix(nside)
+    og = geometry.healpix(nside)
+    rng = np.random.default_rng(11)
+    nal = sht.nalm(lmax)
+    ell = sht.lm_arrays(lmax)[0]
+    alm = rng.standard_normal(nal) / np.sqrt(1.0 + ell)  # red spectrum, like the sky
+    dev = torch.device("cuda")
+    got = crsolve.sht_synth(g, lmax, torch.tensor(alm, device=dev)).cpu().numpy()
+    rings = [0, 1, 7, nside - 2, nside - 1, 2 * nside - 1, 3 * nside + 5, og.nring - 1]
+    sub = _ring_subset(og, np.array(rings))
+    ref = sht.synth(sub, lmax, alm)
+    gs = np.concatenate([got[og.offset[r]:og.offset[r] + og.nphi[r]] for r in rings])
+    assert _rel(gs, ref) < SHT_TOL
+    # adjoint: sampled m, full ring sum in the oracle
+    maps = rng.standard_normal(og.npix)
+    got_a = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
+    ms = [0, 1, 2, lmax // 3, lmax - 1, lmax]
+    Hc = np.zeros((og.nring, lmax + 1))
+    Hs = np.zeros((og.nring, lmax + 1))
+    for r in range(og.nring):
+        phi = og.ring_phi(r)
+        f = maps[og.offset[r]:og.offset[r] + og.nphi[r]]
+        arg = np.outer(phi, ms)
+        Hc[r, ms] = f @ np.cos(arg)
+        Hs[r, ms] = f @ np.sin(arg)
+    sweep = LegendreSweep(og.z, og.sint, lmax)
+    for m in ms:
+        sweep.skip_to(m)
+        lam = sweep.table(m)
+        n = lmax - m + 1
+        o = sht.m_offset(lmax, m)
+        c = 1.0 if m == 0 else math.sqrt(2.0)
+        refc = c * (Hc[:, m] @ lam)
+        assert _rel(got_a[o:o + n], refc) < SHT_TOL, m
+        if m > 0:
+            refs = c * (Hs[:, m] @ lam)
+            assert _rel(got_a[o + n:o + 2 * n], refs) < SHT_TOL, m
