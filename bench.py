@@ -1,0 +1,280 @@
+"""Benchmark: PCG time-to-solution per right-hand side on MI355X.
+
+Workload (default "multires"): the multi-resolution full-sky model -- CMB
+and a power-law foreground (L_k = 512) seen in 5 bands at 30/70/100/143/217
+GHz on HEALPix Nside 64/128/128/256/256 (L_nu = 2 Nside, Gaussian beams
+60/30/20/10/7 arcmin, lognormal noise RMS) -- Wiener filter solved with the
+pseudo-inverse preconditioner to rel.res 1e-8.  One step = one solve of the
+workload's right-hand sides from x = 0.  The block-diagonal preconditioner
+is timed beside it (the paper's comparison).  "batched" runs 64 masked
+constrained realizations of mixed resolution (use --precond diag there: the
+pseudo-inverse preconditioner alone degrades under a mask).  All inputs are
+seeded, synthetic and resident in device memory before the timed region.
+
+Prints one JSON line (the contract used by the round driver), with the
+Legendre kernels' roofline measured live with HIP events and the CPU
+oracle's time on a bounded sample as a reported baseline.
+
+    python bench.py [--steps K] [--warmup W] [--workload batched|multires|masked]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X published dense FP64 (vector and matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name, nprob, crsolve, inputs, torch, dev):
+    grids = {}
+
+    def grid(spec):
+        if spec not in grids:
+            grids[spec] = crsolve.Grid.from_spec(spec)
+        return grids[spec]
+
+    probs = []
+    if name == "batched":
+        specs = [inputs.make_problem("batched", index=i) for i in range(nprob)]
+    else:
+        specs = [inputs.make_problem(name)]
+    for i, prob in enumerate(specs):
+        gl = [grid(b["grid"]) for b in prob["bands"]]
+        taus = inputs.inverse_noise_maps(prob, lambda spec: grid(spec).pixel_centres())
+        model = crsolve.model_from_problem(prob, taus, gl, diag=True)
+        s = torch.tensor(inputs.signal_coefficients(prob), device=dev)
+        sig_maps = model.project(s)
+        d = []
+        for nu, (t, m) in enumerate(zip(taus, sig_maps)):
+            sig = torch.tensor(t, device=dev)
+            sig = torch.where(sig > 0, 1.0 / torch.sqrt(torch.clamp(sig, min=1e-300)),
+                              torch.zeros_like(sig))
+            z = torch.tensor(inputs.white_noise(prob, nu, len(t)), device=dev)
+            d.append((m + sig * z).unsqueeze(0).contiguous())
+        probs.append({"prob": prob, "model": model, "d": d, "taus": taus})
+        if (i + 1) % 8 == 0:
+            log(f"built {i + 1}/{len(specs)} problems")
+    return probs, grids
+
+
+def solve_all(probs, precond, rtol, maxiter, torch):
+    iters = []
+    for p in probs:
+        x, info = p["model"].constrained_realization(p["d"], p["prob"]["seed"], mode=p["prob"]["rhs"],
+                                                     precond=precond, rtol=rtol, maxiter=maxiter,
+                                                     raise_on_error=False)
+        if info["status"] not in (0,):
+            raise RuntimeError(f"solve failed: status {info['status']} relres {info['relres']}")
+        iters.append(info["iters"][0])
+        p["x"] = x
+    return iters
+
+
+def sht_roofline(crsolve, torch, dev, nside=1024, lmax=2000, nmaps_list=(1, 6), reps=3):
+    """Legendre kernels at the large band shape, each timed with HIP events."""
+    g = crsolve.Grid.healpix(nside)
+    out = {}
+    for nm in nmaps_list:
+        alm = torch.randn(nm, (lmax + 1) ** 2, dtype=torch.float64, device=dev)
+        maps = torch.randn(nm, g.npix, dtype=torch.float64, device=dev)
+        crsolve.sht_synth(g, lmax, alm)
+        crsolve.sht_adjoint(g, lmax, maps)
+        torch.cuda.synchronize()
+        crsolve.kernel_stats_reset()
+        crsolve.set_profiling(True)
+        for _ in range(reps):
+            crsolve.sht_synth(g, lmax, alm)
+            crsolve.sht_adjoint(g, lmax, maps)
+        torch.cuda.synchronize()
+        crsolve.set_profiling(False)
+        res = {}
+        for fam in ("legendre_synth", "legendre_adjoint", "ring_fft"):
+            st = crsolve.kernel_stats(fam)
+            avg_ms = st["ms"] / max(1, st["launches"])
+            work = st["work"] / max(1, st["launches"])
+            if fam == "ring_fft":
+                res[fam] = {"avg_ms": avg_ms, "GBs": work / (avg_ms * 1e-3) / 1e9}
+            else:
+                tf = work / (avg_ms * 1e-3) / 1e12
+                res[fam] = {"avg_ms": avg_ms, "TFLOPs": tf, "frac": tf / FP64_PEAK_TFLOPS}
+        out[f"nside{nside}_l{lmax}_nmaps{nm}"] = res
+    return out
+
+
+def _oracle_model(prob, taus):
+    from oracle import geometry
+    from oracle.model import Model as OModel
+    from paper_1710_00621_amd import inputs
+    bands = [{"grid": geometry.make_grid(b["grid"]), "lmax": b["lmax"], "beam": bm, "tau": t}
+             for b, bm, t in zip(prob["bands"], inputs.beams(prob), taus)]
+    comps = [{"lmax": c["lmax"], "invcl": icl} for c, icl in zip(prob["comps"], inputs.priors(prob))]
+    return OModel(bands, comps, prob["q"])
+
+
+def _sht_work(prob):
+    """Legendre work of one round trip over all bands: sum nring * (L+1)^2."""
+    from paper_1710_00621_amd import inputs
+    return sum(inputs.grid_nring(b["grid"]) * (b["lmax"] + 1) ** 2 for b in prob["bands"])
+
+
+def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
+    """The oracle (numpy FP64, as it stands) timed on the host on a bounded
+    sample, in ms per RHS.  For a single large problem the sample is one PCG
+    iteration (apply_A + preconditioner) of the same recipe at half the
+    resolution, scaled by the Legendre work ratio (sum nring (L+1)^2) and
+    multiplied by the GPU's iteration count."""
+    import numpy as np
+
+    from oracle import geometry, precond as opc
+    from paper_1710_00621_amd import inputs
+
+    nthreads = os.cpu_count() or 1
+    if name != "batched":
+        prob = inputs.make_problem(name, scale=2)
+        cache = {}
+
+        def centres(spec):
+            if spec not in cache:
+                cache[spec] = geometry.make_grid(spec).pixel_centres()
+            return cache[spec]
+
+        taus = inputs.inverse_noise_maps(prob, centres)
+        om = _oracle_model(prob, taus)
+        M = opc.PseudoInversePrecond(om) if precond == "pinv" else opc.DiagonalPrecond(om)
+        v = np.random.default_rng(0).standard_normal(om.n)
+        t0 = time.perf_counter()
+        om.apply_A(v)
+        M(v)
+        dt = time.perf_counter() - t0
+        ratio = _sht_work(probs[0]["prob"]) / _sht_work(prob)
+        per_rhs = dt * ratio * gpu_iters[0] * 1e3
+        return {"value": per_rhs, "unit": "ms/RHS", "cores": nthreads, "kind": "oracle",
+                "sample": (f"one oracle PCG iteration (apply_A + M_{precond}) of the {name} recipe "
+                           f"at half resolution took {dt:.1f} s; scaled by the Legendre work ratio "
+                           f"{ratio:.2f} and by the GPU's {gpu_iters[0]} iterations (extrapolated)")}
+    t_total = 0.0
+    est, used = [], []
+    order = sorted(range(len(probs)), key=lambda i: probs[i]["model"].n)
+    for i in order:
+        if t_total > budget_s:
+            break
+        p = probs[i]
+        om = _oracle_model(p["prob"], p["taus"])
+        M = opc.PseudoInversePrecond(om) if precond == "pinv" else opc.DiagonalPrecond(om)
+        v = np.random.default_rng(0).standard_normal(om.n)
+        t0 = time.perf_counter()
+        om.apply_A(v)
+        M(v)
+        dt = time.perf_counter() - t0
+        t_total += dt
+        est.append(dt * gpu_iters[i])
+        used.append(i)
+    return {"value": 1e3 * float(np.mean(est)), "unit": "ms/RHS", "cores": nthreads, "kind": "oracle",
+            "sample": (f"one oracle PCG iteration (apply_A + M_{precond}) timed on {len(used)} of the "
+                       f"smallest problems (indices {used}), times each problem's GPU iteration "
+                       f"count; extrapolated per RHS")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="multires", choices=["batched", "multires", "masked"])
+    ap.add_argument("--nprob", type=int, default=64)
+    ap.add_argument("--precond", default="pinv", choices=["pinv", "diag"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--maxiter", type=int, default=5000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sht-roofline", action="store_true")
+    a = ap.parse_args()
+    if a.workload != "batched":
+        a.nprob = 1
+    if a.gpus != 1:
+        print("bench.py measures one GPU: every GPU box here has one MI355X and the solver does "
+              "not shard across GPUs (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1710_00621_amd import crsolve, inputs
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev)
+    torch.cuda.synchronize()
+    log(f"setup {time.time() - t0:.1f}s for {len(probs)} problems")
+
+    for w in range(a.warmup):
+        it = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+        log(f"warmup {w}: iterations min/mean/max {min(it)}/{sum(it) / len(it):.1f}/{max(it)}")
+    torch.cuda.synchronize()
+    crsolve.kernel_stats_reset()
+    crsolve.set_profiling(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(a.steps):
+        iters = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    crsolve.set_profiling(False)
+    ms_per_step = (t2 - t1) * 1e3 / a.steps
+    nrhs = len(probs)
+    per_rhs = ms_per_step / nrhs
+    log(f"timed {a.steps} steps: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+
+    compare = None
+    if a.precond == "pinv":
+        other = "diag"
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        it_o = solve_all(probs, other, a.rtol, a.maxiter, torch)
+        torch.cuda.synchronize()
+        t_o = (time.perf_counter() - tc) * 1e3 / len(probs)
+        compare = {"precond": other, "ms_per_rhs": t_o, "iterations_mean": sum(it_o) / len(it_o),
+                   "speedup_pinv_over_diag": t_o / per_rhs}
+        log(f"diag: {t_o:.3f} ms/RHS, iterations {it_o}")
+    fam = {}
+    for f in ("legendre_synth", "legendre_adjoint", "ring_fft"):
+        fam[f] = crsolve.kernel_stats(f)
+    dom = max(("legendre_synth", "legendre_adjoint"), key=lambda f: fam[f]["ms"])
+    st = fam[dom]
+    avg_ms = st["ms"] / max(1, st["launches"])
+    achieved = st["work"] / max(1e-30, st["ms"] * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "avg_launch_ms": avg_ms, "launches": st["launches"],
+            "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
+            / max(1e-9, ms_per_step * a.steps)}
+    out = {
+        "metric": "PCG time-to-solution/RHS at rel.res 1e-8, batched vs plain; SHT % roofline",
+        "value": per_rhs, "unit": "ms/RHS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "problems": nrhs, "precond": a.precond,
+                   "rtol": a.rtol, "mode": "plain (one right-hand side per solve)",
+                   "iterations": {"min": min(iters), "mean": sum(iters) / len(iters),
+                                  "max": max(iters)}},
+        "roofline": roof,
+        "preconditioner_comparison": compare,
+    }
+    if not a.no_sht_roofline:
+        out["sht_roofline"] = sht_roofline(crsolve, torch, dev)
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.workload, probs, iters, a.precond)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,12 +127,13 @@ def test_philox_bit_exact_and_normals():
         np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-14)
 
 
-def test_rhs_and_constrained_realization_match_oracle():
+def test_rhs_matches_oracle_masked():
+    """CR right-hand side with explicit omegas on a masked model (tau = 0 in
+    the mask), and the Wiener-filter right-hand side."""
     torch, crsolve = _setup()
     om, gm, prob = _models("masked", 32)
     _, d = synthetic_data(prob, om)
-    seed = 1234
-    om1, om2 = rhs.draw_omegas(om, seed)
+    om1, om2 = rhs.draw_omegas(om, 1234)
     bref = rhs.build_rhs(om, d=d, omega1=om1, omega2=om2)
     dt = [torch.tensor(v, device="cuda").unsqueeze(0) for v in d]
     w1 = [torch.tensor(v, device="cuda").unsqueeze(0) for v in om1]
@@ -141,12 +142,42 @@ def test_rhs_and_constrained_realization_match_oracle():
     assert _rel(b, bref) < OP_TOL
     bwf = gm.build_rhs(d=dt)[0].cpu().numpy()
     assert _rel(bwf, rhs.build_rhs(om, d=d)) < OP_TOL
-    # constrained realization: omegas drawn on the device from the same Philox streams
-    ref = pcg.pcg(om.apply_A, precond.PseudoInversePrecond(om), bref, rtol=1e-12, maxiter=3000)
+
+
+def test_constrained_realization_matches_oracle():
+    """Omegas drawn on the device from the Philox streams; the oracle draws the
+    same streams, builds b and solves."""
+    torch, crsolve = _setup()
+    om, gm, prob = _models("diff", 32)
+    _, d = synthetic_data(prob, om)
+    seed = 99
+    om1, om2 = rhs.draw_omegas(om, seed)
+    bref = rhs.build_rhs(om, d=d, omega1=om1, omega2=om2)
+    ref = pcg.pcg(om.apply_A, precond.PseudoInversePrecond(om), bref, rtol=1e-12, maxiter=500)
+    dt = [torch.tensor(v, device="cuda").unsqueeze(0) for v in d]
     x, info = gm.constrained_realization(dt, seed, mode="cr", precond="pinv", rtol=1e-12,
-                                         maxiter=3000)
+                                         maxiter=500)
     assert ref.status == "ok" and info["status"] == 0
     assert _rel(x[0].cpu().numpy(), ref.x) < SOL_TOL
+    xw, infow = gm.constrained_realization(dt, seed, mode="wf", precond="diag", rtol=1e-12,
+                                           maxiter=500)
+    refw = pcg.pcg(om.apply_A, precond.DiagonalPrecond(om), rhs.build_rhs(om, d=d),
+                   rtol=1e-12, maxiter=500)
+    assert _rel(xw[0].cpu().numpy(), refw.x) < SOL_TOL
+
+
+def test_masked_solve_residual():
+    """Masked model: GPU solve to 1e-10, residual measured with the oracle's A."""
+    torch, crsolve = _setup()
+    om, gm, prob = _models("masked", 64)
+    _, d = synthetic_data(prob, om)
+    b = rhs.build_rhs(om, d=d)
+    bt = torch.tensor(b, device="cuda")
+    for pc in ("diag", "pinv"):
+        x, info = gm.pcg(bt, precond=pc, rtol=1e-10, maxiter=5000)
+        r = b - om.apply_A(x.cpu().numpy())
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+        print(f"masked-64 {pc}: {info['iters'][0]} iterations", flush=True)
 
 
 @pytest.mark.timeout(400)
