@@ -98,6 +98,8 @@ RingArgs ring_args(crs_grid g, int lmax) {
   r.tw = g->d_tw.p;
   r.nring = g->nring;
   r.lmax = lmax;
+  r.maxn = g->ring_maxn;
+  r.maxp = g->ring_maxp;
   return r;
 }
 
@@ -200,7 +202,7 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
     }
     {
       ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_SYNTH), s);
-      launch_ring(ring_args(g, lmax), RING_SYNTH, nmaps, w.phase.p, pst, nullptr, map, map_stride,
+      launch_ring(g, lmax, RING_SYNTH, nmaps, w.phase.p, pst, nullptr, map, map_stride,
                   nullptr, 1, s);
     }
     return CRS_OK;
@@ -219,12 +221,12 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     GridWork& w = *g->work;
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
     const int64_t pst = (int64_t)g->nring * (lmax + 1);
-    const int ntiles = leg_adjoint_tiles(p.npairs);
+    const int ntiles = leg_adjoint_tiles(p.npairs, lmax);
     w.phase.alloc((size_t)nmaps * pst);
     w.vpart.alloc((size_t)ntiles * nmaps * nalm);
     {
       ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_ADJOINT), s);
-      launch_ring(ring_args(g, lmax), RING_ADJOINT, nmaps, w.phase.p, pst, map, nullptr, map_stride,
+      launch_ring(g, lmax, RING_ADJOINT, nmaps, w.phase.p, pst, map, nullptr, map_stride,
                   nullptr, 1, s);
     }
     {

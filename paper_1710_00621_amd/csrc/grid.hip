@@ -117,7 +117,11 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     auto f = factorize(n);
     CRS_CHECK((int)f.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
     nfac[r] = (int)f.size();
-    for (size_t i = 0; i < f.size(); ++i) fac[(size_t)r * kMaxFactors + i] = f[i];
+    for (size_t i = 0; i < f.size(); ++i) {
+      fac[(size_t)r * kMaxFactors + i] = f[i];
+      if (f[i] > 7) g->ring_maxp = std::max(g->ring_maxp, f[i]);
+    }
+    g->ring_maxn = std::max(g->ring_maxn, n);
     auto it = tw_of.find(n);
     if (it == tw_of.end()) {
       int64_t o = (int64_t)tw.size();
@@ -131,6 +135,30 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     } else {
       twoff[r] = it->second;
     }
+  }
+  // launch classes: prime stage > 7 first, then by ring length
+  g->ring_classes.assign(4, RingClass{});
+  for (int r = 0; r < nr; ++r) {
+    bool gen = false;
+    int mp = 0;
+    for (int i = 0; i < nfac[r]; ++i) {
+      const int f = fac[(size_t)r * kMaxFactors + i];
+      if (f > 7) {
+        gen = true;
+        mp = std::max(mp, f);
+      }
+    }
+    const int n = g->nphi[r];
+    const int c = (gen ? 0 : 2) + (n > 2048 ? 0 : 1);
+    RingClass& rc = g->ring_classes[c];
+    rc.rings.push_back(r);
+    rc.maxn = std::max(rc.maxn, n);
+    rc.maxp = std::max(rc.maxp, mp);
+  }
+  g->d_ring_class.clear();
+  for (auto& rc : g->ring_classes) {
+    g->d_ring_class.emplace_back();
+    g->d_ring_class.back().upload(rc.rings, s);
   }
   int np = (nr + 1) / 2;
   std::vector<double> zp(np), sp(np);

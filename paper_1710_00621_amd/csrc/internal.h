@@ -110,6 +110,13 @@ struct ShtPlan {
   std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
 };
 
+// Rings are launched in classes of similar LDS need: (needs a prime radix
+// stage > 7) x (Nphi > 2048); classes with prime stages go first.
+struct RingClass {
+  std::vector<int> rings;
+  int maxn = 1, maxp = 0;
+};
+
 // Workspace of the public transforms (sht_synth / sht_adjoint).
 struct GridWork {
   DevBuf<double> uhat;
@@ -132,6 +139,9 @@ struct crs_grid_s {
   crs::DevBuf<double> d_zpair;    // z of the north ring of each pair
   crs::DevBuf<double> d_spair;    // sin(theta) of the north ring of each pair
   crs::DevBuf<double2> d_tw;      // twiddles exp(-2 pi i t / N) per distinct N
+  int ring_maxn = 1, ring_maxp = 0;
+  std::vector<crs::RingClass> ring_classes;
+  std::vector<crs::DevBuf<int>> d_ring_class;
   std::map<int, std::unique_ptr<crs::ShtPlan>> plans;
   std::unique_ptr<crs::GridWork> work;
   int device = 0;
@@ -154,7 +164,7 @@ struct LegArgs {
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s);
 // Adjoint: writes ntiles partial vectors vpart[tile][map][nalm]; returns ntiles.
-int leg_adjoint_tiles(int npairs);
+int leg_adjoint_tiles(int npairs, int lmax);
 void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s);
@@ -171,9 +181,11 @@ struct RingArgs {
   const int64_t* twoff;
   const double2* tw;
   int nring, lmax;
+  int maxn, maxp;  // longest ring; largest prime radix above 7 (0 if none)
+  const int* rings;  // ring list of the launch (set by launch_ring per class)
 };
 // maps j = 0..nmaps-1 use weight weights[j / maps_per_weight] (RING_ROUNDTRIP).
-void launch_ring(const RingArgs& a, RingMode mode, int nmaps, double2* phase, int64_t pstride,
+void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase, int64_t pstride,
                  const double* map_in, double* map_out, int64_t mstride,
                  const double* const* weights, int maps_per_weight, hipStream_t s);
 

@@ -17,7 +17,10 @@
 // wave start at different l: the wave runs one recurrence step per l for
 // all lanes and, at the (wave-uniform) l where some lane starts, injects
 // that lane's start values.
+#include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -50,227 +53,344 @@ __device__ __forceinline__ int64_t tri(int L, int m) {
   return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2;
 }
 
+// ------------------------------------------------------- per-wave stepper
+// A wave owns R groups of 64 ring pairs: pair of group j on lane t is
+// base + 64 j + t (j = 0 most polar).  Per group the wave keeps the lanes'
+// recurrence state and two wave-uniform numbers: lw (first l any lane of the
+// group evaluates, forced non-increasing in j so that the groups running at
+// a given l are a suffix j >= q) and nx (next l where some lane of the group
+// starts).  Between start events all running groups step in lockstep.
+template <int R>
+struct Grp {
+  double z[R], a0[R], a1[R];
+  int ls[R];
+  int lw[R];
+  int nx[R];
+};
+
+template <int R>
+__device__ __forceinline__ void grp_init(Grp<R>& G, const LegArgs& a, int m, int base, int lane) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int p = base + 64 * j + lane;
+    const bool valid = p < a.npairs;
+    G.z[j] = a.zpair[valid ? p : a.npairs - 1];
+    G.ls[j] = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
+    G.a0[j] = 0.0;
+    G.a1[j] = 0.0;
+    const int w = wave_min(G.ls[j]);
+    G.nx[j] = w;
+    G.lw[j] = (j == 0) ? w : min(w, G.lw[j - 1]);
+  }
+}
+
+// first running group at l (lw[R-1] <= l is required)
+template <int R>
+__device__ __forceinline__ int grp_first(const Grp<R>& G, int l) {
+  int q = R - 1;
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j)
+    if (G.lw[j] <= l) q = j;
+  return q;
+}
+
+template <int R>
+__device__ __forceinline__ int grp_next_event(const Grp<R>& G, int q) {
+  int ne = INT_MAX;
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (j >= q) ne = min(ne, G.nx[j]);
+  return ne;
+}
+
+template <int R>
+__device__ __forceinline__ int grp_next_start(const Grp<R>& G, int q, int L) {
+  int pe = L + 1;
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (j == q - 1) pe = G.lw[j];
+  return pe;
+}
+
+// One step of group j at l with start injection (event step).
+template <int R>
+__device__ __forceinline__ double grp_event_step(Grp<R>& G, int j, const LegArgs& a, int m, int base,
+                                                 int lane, int l, double gl) {
+  double c = fma(gl * G.z[j], G.a1[j], -G.a0[j]);
+  double pv = G.a1[j];
+  if (l == G.nx[j]) {
+    if (G.ls[j] == l) {
+      const double2 ms = a.ms[(size_t)m * a.npairs + base + 64 * j + lane];
+      c = ms.y;
+      pv = ms.x;
+    }
+    G.nx[j] = wave_min(G.ls[j] > l ? G.ls[j] : INT_MAX);
+  }
+  G.a0[j] = pv;
+  G.a1[j] = c;
+  return c;
+}
+
 // ------------------------------------------------------------- synthesis
-template <int NM, bool HAS_S>
-__device__ __forceinline__ void synth_body(const LegArgs& a, int m, int p, bool valid, int nmaps,
-                                           int map0, const double* __restrict__ uhat,
-                                           int64_t ustride, double2* __restrict__ phase,
-                                           int64_t pstride) {
+// Accumulators X (parity of the next step) and Y (the other parity): every
+// step adds into X and then swaps X and Y, so consecutive steps need no
+// parity test (the swap is free inside unrolled pairs).  At the end X holds
+// the sum over l with l - m of the parity of L + 1 - m.
+template <int NM, int R>
+struct SynAcc {
+  double X[R][NM][2], Y[R][NM][2];  // [group][map][cos, sin]
+};
+
+template <int NM, int R>
+__device__ __forceinline__ void syn_swap(SynAcc<NM, R>& A) {
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double t = A.X[j][k][c];
+        A.X[j][k][c] = A.Y[j][k][c];
+        A.Y[j][k][c] = t;
+      }
+}
+
+// one step for groups J0..R-1 into X (no swap)
+template <int NM, int R, int J0, bool HAS_S>
+__device__ __forceinline__ void syn_acc(SynAcc<NM, R>& A, Grp<R>& G, double gl, const double* uc,
+                                        const double* us) {
+#pragma unroll
+  for (int j = J0; j < R; ++j) {
+    const double c = fma(gl * G.z[j], G.a1[j], -G.a0[j]);
+    G.a0[j] = G.a1[j];
+    G.a1[j] = c;
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      A.X[j][k][0] = fma(c, uc[k], A.X[j][k][0]);
+      if (HAS_S) A.X[j][k][1] = fma(c, us[k], A.X[j][k][1]);
+    }
+  }
+}
+
+template <int NM, int R, int NA, bool HAS_S>
+__device__ __forceinline__ void syn_plain(SynAcc<NM, R>& A, Grp<R>& G, cdouble* gb, cdouble* const* ub,
+                                          int nsl, int l, int stop) {
+  constexpr int J0 = R - NA;
+  constexpr int B = (NM == 1) ? 8 : ((NM == 2) ? 4 : 2);
+  for (; l + B <= stop; l += B) {
+    l = __builtin_amdgcn_readfirstlane(l);
+    cdouble* gp = gb + l;
+    double gv[B], uc[B][NM], us[B][NM];
+#pragma unroll
+    for (int i = 0; i < B; ++i) gv[i] = gp[i];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      cdouble* up = ub[k] + l;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        uc[i][k] = up[i];
+        us[i][k] = HAS_S ? up[i + nsl] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      syn_acc<NM, R, J0, HAS_S>(A, G, gv[i], uc[i], us[i]);
+      syn_swap<NM, R>(A);
+    }
+  }
+  for (; l < stop; ++l) {
+    double uc[NM], us[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      uc[k] = uld(ub[k], l);
+      us[k] = HAS_S ? uld(ub[k], l + nsl) : 0.0;
+    }
+    syn_acc<NM, R, J0, HAS_S>(A, G, uld(gb, l), uc, us);
+    syn_swap<NM, R>(A);
+  }
+}
+
+template <int NM, int R, int NA, bool HAS_S>
+__device__ __forceinline__ void syn_event(SynAcc<NM, R>& A, Grp<R>& G, const LegArgs& a, int m, int base,
+                                          int lane, cdouble* gb, cdouble* const* ub, int nsl, int l) {
+  constexpr int J0 = R - NA;
+  const double gl = uld(gb, l);
+  double uc[NM], us[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    uc[k] = uld(ub[k], l);
+    us[k] = HAS_S ? uld(ub[k], l + nsl) : 0.0;
+  }
+#pragma unroll
+  for (int j = J0; j < R; ++j) {
+    const double c = grp_event_step<R>(G, j, a, m, base, lane, l, gl);
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      A.X[j][k][0] = fma(c, uc[k], A.X[j][k][0]);
+      if (HAS_S) A.X[j][k][1] = fma(c, us[k], A.X[j][k][1]);
+    }
+  }
+  syn_swap<NM, R>(A);
+}
+
+template <int NM, int R, bool HAS_S>
+__device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, int lane, int nmaps, int map0,
+                                           const double* __restrict__ uhat, int64_t ustride,
+                                           double2* __restrict__ phase, int64_t pstride) {
   const int L = a.lmax;
-  const int pc = valid ? p : a.npairs - 1;
-  const double z = a.zpair[pc];
-  const int ls = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
-  const double2 ms = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
   cdouble* gb = as_const(a.g + tri(L, m) - m);
   const int nsl = L - m + 1;
   cdouble* ub[NM];
 #pragma unroll
-  for (int j = 0; j < NM; ++j) {
-    int mj = min(map0 + j, nmaps - 1);
-    ub[j] = as_const(uhat + (int64_t)mj * ustride + moff(L, m) - m);
+  for (int k = 0; k < NM; ++k)
+    ub[k] = as_const(uhat + (int64_t)min(map0 + k, nmaps - 1) * ustride + moff(L, m) - m);
+  Grp<R> G;
+  grp_init<R>(G, a, m, base, lane);
+  SynAcc<NM, R> A;
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+#pragma unroll
+    for (int k = 0; k < NM; ++k) A.X[j][k][0] = A.X[j][k][1] = A.Y[j][k][0] = A.Y[j][k][1] = 0.0;
+  int l = G.lw[R - 1];
+  while (l <= L) {
+    const int q = grp_first<R>(G, l);
+    const int ne = grp_next_event<R>(G, q);
+    if (ne == l) {
+      switch (R - q) {
+#define SYN_EV(NA) case NA: if (NA <= R) syn_event<NM, R, (NA <= R ? NA : R), HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l); break;
+        SYN_EV(1) SYN_EV(2) SYN_EV(3) SYN_EV(4)
+#undef SYN_EV
+      }
+      ++l;
+      continue;
+    }
+    const int stop = min(min(grp_next_start<R>(G, q, L), ne), L + 1);
+    switch (R - q) {
+#define SYN_PL(NA) case NA: if (NA <= R) syn_plain<NM, R, (NA <= R ? NA : R), HAS_S>(A, G, gb, ub, nsl, l, stop); break;
+      SYN_PL(1) SYN_PL(2) SYN_PL(3) SYN_PL(4)
+#undef SYN_PL
+    }
+    l = stop;
   }
-  double Ec[NM], Es[NM], Oc[NM], Os[NM];
+  // X holds parity (L + 1 - m) & 1 (the loop always ends at l = L + 1, or
+  // never ran, in which case X = Y = 0)
+  const bool x_is_odd = ((L + 1 - m) & 1) != 0;
 #pragma unroll
-  for (int j = 0; j < NM; ++j) Ec[j] = Es[j] = Oc[j] = Os[j] = 0.0;
-
-  int l = wave_min(ls);
-  if (l <= L) {
-    double a0 = 0.0, a1 = 0.0;  // mu_{l-2}, mu_{l-1}
-    int next = l;
-    auto accE = [&](double c, int ll) {
+  for (int j = 0; j < R; ++j) {
+    const int p = base + 64 * j + lane;
+    const int rs = a.nring - 1 - p;
 #pragma unroll
-      for (int j = 0; j < NM; ++j) {
-        Ec[j] = fma(c, uld(ub[j], ll), Ec[j]);
-        if (HAS_S) Es[j] = fma(c, uld(ub[j], ll + nsl), Es[j]);
-      }
-    };
-    auto accO = [&](double c, int ll) {
-#pragma unroll
-      for (int j = 0; j < NM; ++j) {
-        Oc[j] = fma(c, uld(ub[j], ll), Oc[j]);
-        if (HAS_S) Os[j] = fma(c, uld(ub[j], ll + nsl), Os[j]);
-      }
-    };
-    while (l <= L) {
-      if (l == next) {
-        double c = fma(uld(gb, l) * z, a1, -a0);
-        const bool inj = (ls == l);
-        c = inj ? ms.y : c;
-        const double pv = inj ? ms.x : a1;
-        if ((l - m) & 1) accO(c, l); else accE(c, l);
-        a0 = pv;
-        a1 = c;
-        ++l;
-        next = wave_min(ls >= l ? ls : INT_MAX);
-        continue;
-      }
-      const int stop = min(next, L + 1);
-      if (((l - m) & 1) && l < stop) {
-        double c = fma(uld(gb, l) * z, a1, -a0);
-        accO(c, l);
-        a0 = a1;
-        a1 = c;
-        ++l;
-      }
-      // blocks of B steps starting at even l - m; coefficients of a block are
-      // fetched with a few wide scalar loads before the block's arithmetic
-      constexpr int B = (NM == 1) ? 8 : ((NM == 2) ? 4 : 2);
-      for (; l + B <= stop; l += B) {
-        l = __builtin_amdgcn_readfirstlane(l);
-        cdouble* gp = gb + l;
-        double gv[B], uc[NM][B], us[NM][B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) gv[i] = gp[i];
-#pragma unroll
-        for (int j = 0; j < NM; ++j) {
-          cdouble* up = ub[j] + l;
-#pragma unroll
-          for (int i = 0; i < B; ++i) {
-            uc[j][i] = up[i];
-            us[j][i] = HAS_S ? up[i + nsl] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          const double c = fma(gv[i] * z, a1, -a0);
-          a0 = a1;
-          a1 = c;
-#pragma unroll
-          for (int j = 0; j < NM; ++j) {
-            if (i & 1) {
-              Oc[j] = fma(c, uc[j][i], Oc[j]);
-              if (HAS_S) Os[j] = fma(c, us[j][i], Os[j]);
-            } else {
-              Ec[j] = fma(c, uc[j][i], Ec[j]);
-              if (HAS_S) Es[j] = fma(c, us[j][i], Es[j]);
-            }
-          }
-        }
-      }
-      for (; l < stop; ++l) {
-        double c = fma(uld(gb, l) * z, a1, -a0);
-        if ((l - m) & 1) accO(c, l); else accE(c, l);
-        a0 = a1;
-        a1 = c;
+    for (int k = 0; k < NM; ++k) {
+      const double ec = x_is_odd ? A.Y[j][k][0] : A.X[j][k][0];
+      const double es = x_is_odd ? A.Y[j][k][1] : A.X[j][k][1];
+      const double oc = x_is_odd ? A.X[j][k][0] : A.Y[j][k][0];
+      const double os = x_is_odd ? A.X[j][k][1] : A.Y[j][k][1];
+      if (p < a.npairs && map0 + k < nmaps) {
+        double2* ph = phase + (int64_t)(map0 + k) * pstride;
+        ph[(int64_t)p * (L + 1) + m] = make_double2(ec + oc, es + os);
+        if (rs != p) ph[(int64_t)rs * (L + 1) + m] = make_double2(ec - oc, es - os);
       }
     }
   }
-  if (!valid) return;
-  const int rs = a.nring - 1 - p;
-#pragma unroll
-  for (int j = 0; j < NM; ++j) {
-    if (map0 + j >= nmaps) break;
-    double2* ph = phase + (int64_t)(map0 + j) * pstride;
-    ph[(int64_t)p * (L + 1) + m] = make_double2(Ec[j] + Oc[j], Es[j] + Os[j]);
-    if (rs != p) ph[(int64_t)rs * (L + 1) + m] = make_double2(Ec[j] - Oc[j], Es[j] - Os[j]);
-  }
 }
 
-template <int NM>
+// XCD-aware order: the 8 XCDs take blocks round-robin; consecutive blocks on
+// one XCD share an m-block (same harmonic coefficients, one L2) and small m
+// (the longest recurrences) are dispatched first.  Wave w of a block takes
+// m = 4 mb + w.
+__device__ __forceinline__ void block_coords(int ntiles, int& mb, int& tile) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7, q = b >> 3;
+  tile = q % ntiles;
+  mb = (q / ntiles) * 8 + xcd;
+}
+
+template <int NM, int R>
 __global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const double* __restrict__ uhat,
                                                    int64_t ustride, double2* __restrict__ phase,
                                                    int64_t pstride, int ntiles) {
-  // XCD-aware order: the 8 XCDs take blocks round-robin; consecutive blocks
-  // on one XCD share an m-block (same harmonic coefficients, one L2), and
-  // small m (the longest recurrences) are dispatched first.
-  const int b = blockIdx.x;
-  const int xcd = b & 7, q = b >> 3;
-  const int tile = q % ntiles;
-  const int mb = (q / ntiles) * 8 + xcd;
+  int mb, tile;
+  block_coords(ntiles, mb, tile);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int m = mb * 4 + wave;
   if (m > a.lmax) return;
-  const int p = tile * 64 + (threadIdx.x & 63);
-  const bool valid = p < a.npairs;
+  const int lane = threadIdx.x & 63;
+  const int base = tile * 64 * R;
   const int map0 = blockIdx.y * NM;
   if (m == 0)
-    synth_body<NM, false>(a, m, p, valid, nmaps, map0, uhat, ustride, phase, pstride);
+    synth_wave<NM, R, false>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
   else
-    synth_body<NM, true>(a, m, p, valid, nmaps, map0, uhat, ustride, phase, pstride);
+    synth_wave<NM, R, true>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
 }
 
 // --------------------------------------------------------------- adjoint
-// Block: one m, 256 lanes, R adjacent ring pairs per lane (pair = tile*256R + tid*R + j).
-// Per l each lane sums its R products; the 256 lane sums are reduced through
-// LDS every CH steps (fixed order, deterministic) and written as the tile's
-// partial v^.
-template <int NM, int R, int CH, bool SQ, bool HAS_S, bool ODD0>
-__device__ __forceinline__ void adj_chunk_fast(cdouble* gb, int lc, int L,
-                                               const double (&z)[R], double (&a0)[R], double (&a1)[R],
-                                               const double (&E)[R][NM][2], const double (&O)[R][NM][2],
-                                               double (&P)[CH][NM][2]) {
-  double gv[CH];
-  cdouble* gp = gb + __builtin_amdgcn_readfirstlane(lc);
-#pragma unroll
-  for (int s = 0; s < CH; ++s) gv[s] = (lc + s <= L) ? gp[s] : 0.0;
+// Same wave decomposition.  Per l every lane sums its groups' products into
+// P[s]; each chunk of CH steps is reduced over the wave's 64 lanes through a
+// wave-private LDS block (no block barrier) in a fixed order and written as
+// the wave's partial v^ (one partial per ring tile of 64 R pairs).
+template <int NM>
+struct AdjCfg {
+  static constexpr int CH = (8 / NM) < 1 ? 1 : (8 / NM);
+  static constexpr int NOUT = CH * NM * 2;
+};
+
+template <int NM, int R, int NA, bool FAST, bool ODD0, bool SQ, bool HAS_S>
+__device__ __forceinline__ void adj_chunk(Grp<R>& G, const double (&E)[R][NM][2], const double (&O)[R][NM][2],
+                                          const double (&gv)[AdjCfg<NM>::CH], const LegArgs& a, int m,
+                                          int base, int lane, int lc, int L,
+                                          double (&P)[AdjCfg<NM>::CH][NM][2]) {
+  constexpr int CH = AdjCfg<NM>::CH;
+  constexpr int J0 = R - NA;
 #pragma unroll
   for (int s = 0; s < CH; ++s) {
     const int l = lc + s;
     if (l > L) break;
-    const double gl = gv[s];
+    const bool odd = ODD0 ^ ((s & 1) != 0);
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double c = fma(gl * z[j], a1[j], -a0[j]);
-      a0[j] = a1[j];
-      a1[j] = c;
-      const bool odd = ODD0 ^ (s & 1);
+    for (int j = J0; j < R; ++j) {
+      double c;
+      if (FAST) {
+        c = fma(gv[s] * G.z[j], G.a1[j], -G.a0[j]);
+        G.a0[j] = G.a1[j];
+        G.a1[j] = c;
+      } else {
+        c = grp_event_step<R>(G, j, a, m, base, lane, l, gv[s]);
+      }
       const double w = SQ ? c * c : c;
 #pragma unroll
       for (int k = 0; k < NM; ++k) {
-        const double hc = (SQ || !odd) ? E[j][k][0] : O[j][k][0];
-        P[s][k][0] = fma(w, hc, P[s][k][0]);
-        if (HAS_S) {
-          const double hs = (SQ || !odd) ? E[j][k][1] : O[j][k][1];
-          P[s][k][1] = fma(w, hs, P[s][k][1]);
-        }
+        P[s][k][0] = fma(w, (SQ || !odd) ? E[j][k][0] : O[j][k][0], P[s][k][0]);
+        if (HAS_S) P[s][k][1] = fma(w, (SQ || !odd) ? E[j][k][1] : O[j][k][1], P[s][k][1]);
       }
     }
   }
 }
 
-template <int NM>
-struct AdjShared {
-  static constexpr int CH = (8 / NM) < 1 ? 1 : (8 / NM);
-  static constexpr int NOUT = CH * NM * 2;
-  double buf[NOUT][257];
-  double red[4][NOUT];
-  int smin[4];
-};
-
 template <int NM, int R, bool SQ, bool HAS_S>
-__device__ __forceinline__ void adjoint_body(const LegArgs& a, int m, int tile, int map0, int nmaps,
+__device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, int lane, int nmaps, int map0,
                                              const double2* __restrict__ phase, int64_t pstride,
-                                             double* __restrict__ vpart, int64_t vstride,
-                                             int64_t tstride, AdjShared<NM>& sh) {
-  constexpr int CH = AdjShared<NM>::CH;
-  constexpr int NOUT = AdjShared<NM>::NOUT;
-  static_assert(NOUT <= 64 && (NOUT & (NOUT - 1)) == 0, "NOUT must be a power of two <= 64");
-  auto& buf = sh.buf;
-  auto& red = sh.red;
-  auto& smin = sh.smin;
+                                             double* __restrict__ vpart, int64_t vstride, int64_t tstride,
+                                             double* __restrict__ wb) {
+  constexpr int CH = AdjCfg<NM>::CH;
+  constexpr int NOUT = AdjCfg<NM>::NOUT;
+  static_assert(NOUT == 16, "wave reduction assumes 16 outputs per chunk");
   const int L = a.lmax;
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int base = tile * 64 * R;
   cdouble* gb = as_const(a.g + tri(L, m) - m);
-
-  double z[R], a0[R], a1[R];
+  Grp<R> G;
+  grp_init<R>(G, a, m, base, lane);
   double E[R][NM][2], O[R][NM][2];
-  int lw[R], nx[R];
-  const int pbase = tile * 256 * R + tid * R;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int p = pbase + j;
+    const int p = base + 64 * j + lane;
     const bool valid = p < a.npairs;
     const int pc = valid ? p : a.npairs - 1;
-    z[j] = a.zpair[pc];
-    const int lsj = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
     const int rs = a.nring - 1 - pc;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-      const int mk = min(map0 + k, nmaps - 1);
-      const double2* ph = phase + (int64_t)mk * pstride;
-      double2 hn = valid ? ph[(int64_t)pc * (L + 1) + m] : make_double2(0.0, 0.0);
-      double2 hs = (valid && rs != pc) ? ph[(int64_t)rs * (L + 1) + m] : make_double2(0.0, 0.0);
+      const double2* ph = phase + (int64_t)min(map0 + k, nmaps - 1) * pstride;
+      const double2 hn = valid ? ph[(int64_t)pc * (L + 1) + m] : make_double2(0.0, 0.0);
+      const double2 hs = (valid && rs != pc) ? ph[(int64_t)rs * (L + 1) + m] : make_double2(0.0, 0.0);
       if (valid && rs == pc) {
         // equator ring: its own pair, lambda(z) H for both parities
         E[j][k][0] = hn.x; E[j][k][1] = hn.y;
@@ -280,119 +400,69 @@ __device__ __forceinline__ void adjoint_body(const LegArgs& a, int m, int tile, 
         O[j][k][0] = hn.x - hs.x; O[j][k][1] = hn.y - hs.y;
       }
     }
-    a0[j] = 0.0;
-    a1[j] = 0.0;
-    lw[j] = wave_min(lsj);
-    nx[j] = lw[j];
-  }
-  int lwm = INT_MAX;
-#pragma unroll
-  for (int j = 0; j < R; ++j) lwm = min(lwm, lw[j]);
-  if ((tid & 63) == 0) smin[wave] = lwm;
-  __syncthreads();
-  int l0 = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
-  l0 = max(l0, m);
-  if (l0 > L + 1) l0 = L + 1;
-  // zero-fill the part of this tile's output that no ring reaches
-  {
-    const int nl = l0 - m;
-    const int nsl = L - m + 1;
-    for (int i = tid; i < nl * NM * 2; i += 256) {
-      const int ll = i % nl, rest = i / nl, cs = rest & 1, k = rest >> 1;
-      if (cs == 1 && !HAS_S) continue;
-      if (map0 + k >= nmaps) continue;
-      vpart[(int64_t)tile * tstride + (int64_t)(map0 + k) * vstride + moff(L, m) + cs * nsl + ll] = 0.0;
-    }
   }
   const int nsl = L - m + 1;
+  double* const vbase = vpart + (int64_t)tile * tstride + moff(L, m);
+  int l0 = G.lw[R - 1];
+  if (l0 < m) l0 = m;
+  if (l0 > L + 1) l0 = L + 1;
+  // zero-fill this tile's output below the first evaluated l
+  for (int i = lane; i < (l0 - m) * NM * 2; i += 64) {
+    const int nl = l0 - m;
+    const int ll = i % nl, rest = i / nl, cs = rest & 1, k = rest >> 1;
+    if ((cs == 1 && !HAS_S) || map0 + k >= nmaps) continue;
+    vbase[(int64_t)(map0 + k) * vstride + cs * nsl + ll] = 0.0;
+  }
   for (int lc = l0; lc <= L; lc += CH) {
+    const int lend = min(lc + CH - 1, L);
+    const int q = grp_first<R>(G, lend);
+    const bool fast = grp_next_event<R>(G, q) > lend;
+    const bool odd0 = ((lc - m) & 1) != 0;
+    double gv[CH];
+    cdouble* gp = gb + __builtin_amdgcn_readfirstlane(lc);
+#pragma unroll
+    for (int s = 0; s < CH; ++s) gv[s] = (lc + s <= L) ? gp[s] : 0.0;
     double P[CH][NM][2];
 #pragma unroll
     for (int s = 0; s < CH; ++s)
 #pragma unroll
       for (int k = 0; k < NM; ++k) P[s][k][0] = P[s][k][1] = 0.0;
-    bool fast = true;
-#pragma unroll
-    for (int j = 0; j < R; ++j) fast = fast && (lw[j] <= lc) && (nx[j] >= lc + CH);
-    const bool odd0 = ((lc - m) & 1) != 0;
-    if (fast) {
-      if (odd0)
-        adj_chunk_fast<NM, R, CH, SQ, HAS_S, true>(gb, lc, L, z, a0, a1, E, O, P);
-      else
-        adj_chunk_fast<NM, R, CH, SQ, HAS_S, false>(gb, lc, L, z, a0, a1, E, O, P);
-    } else {
-#pragma unroll
-      for (int s = 0; s < CH; ++s) {
-        const int l = lc + s;
-        if (l > L) break;
-        const double gl = uld(gb, l);
-        const bool odd = ((l - m) & 1) != 0;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          if (l < lw[j]) continue;
-          double c = fma(gl * z[j], a1[j], -a0[j]);
-          double pv = a1[j];
-          if (l == nx[j]) {
-            // start values are re-read at these (rare) events to keep them
-            // out of registers
-            const int p = pbase + j;
-            const bool valid = p < a.npairs;
-            const int lsj = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
-            const bool inj = (lsj == l);
-            if (inj) {
-              const double2 msj = a.ms[(size_t)m * a.npairs + p];
-              c = msj.y;
-              pv = msj.x;
-            }
-            nx[j] = wave_min(lsj > l ? lsj : INT_MAX);
-          }
-          a0[j] = pv;
-          a1[j] = c;
-          const double w = SQ ? c * c : c;
-#pragma unroll
-          for (int k = 0; k < NM; ++k) {
-            const double hc = (SQ || !odd) ? E[j][k][0] : O[j][k][0];
-            P[s][k][0] = fma(w, hc, P[s][k][0]);
-            if (HAS_S) {
-              const double hs = (SQ || !odd) ? E[j][k][1] : O[j][k][1];
-              P[s][k][1] = fma(w, hs, P[s][k][1]);
-            }
-          }
-        }
-      }
-    }
+#define ADJ_CASE(NA)                                                                                  \
+  case NA:                                                                                            \
+    if (NA <= R) {                                                                                    \
+      constexpr int NAc = NA <= R ? NA : R;                                                           \
+      if (fast) {                                                                                     \
+        if (odd0) adj_chunk<NM, R, NAc, true, true, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);   \
+        else adj_chunk<NM, R, NAc, true, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);       \
+      } else {                                                                                        \
+        if (odd0) adj_chunk<NM, R, NAc, false, true, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);  \
+        else adj_chunk<NM, R, NAc, false, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);      \
+      }                                                                                               \
+    }                                                                                                 \
+    break;
+    switch (R - q) { ADJ_CASE(1) ADJ_CASE(2) ADJ_CASE(3) ADJ_CASE(4) }
+#undef ADJ_CASE
+    // wave-private reduction: wb is [NOUT][65]
 #pragma unroll
     for (int s = 0; s < CH; ++s)
 #pragma unroll
       for (int k = 0; k < NM; ++k) {
-        buf[(s * NM + k) * 2 + 0][tid] = P[s][k][0];
-        buf[(s * NM + k) * 2 + 1][tid] = P[s][k][1];
+        wb[((s * NM + k) * 2 + 0) * 65 + lane] = P[s][k][0];
+        wb[((s * NM + k) * 2 + 1) * 65 + lane] = P[s][k][1];
       }
-    __syncthreads();
-    {
-      // NOUT outputs, NPER = 256 / NOUT threads each: every thread sums NOUT
-      // lane values, lanes of a wave combine by xor-shuffles, the 4 wave
-      // partials are added in a fixed order.
-      constexpr int NPER = 256 / NOUT;
-      const int o = tid % NOUT;
-      const int sub = tid / NOUT;
-      double acc = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int o = lane & 15, sub = lane >> 4;
+    double acc = 0.0;
 #pragma unroll
-      for (int i = 0; i < NOUT; ++i) acc += buf[o][sub + NPER * i];
-#pragma unroll
-      for (int off = NOUT; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      if ((tid & 63) < NOUT) red[wave][o] = acc;
-    }
-    __syncthreads();
-    if (tid < NOUT) {
-      const int o = tid;
-      const double acc = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
-      const int s = o / (NM * 2);
-      const int k = (o / 2) % NM;
-      const int cs = o & 1;
+    for (int i = 0; i < 16; ++i) acc += wb[o * 65 + sub + 4 * i];
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    __builtin_amdgcn_wave_barrier();
+    if (sub == 0) {
+      const int s = o / (NM * 2), k = (o >> 1) % NM, cs = o & 1;
       const int l = lc + s;
       if (l <= L && map0 + k < nmaps && (HAS_S || cs == 0))
-        vpart[(int64_t)tile * tstride + (int64_t)(map0 + k) * vstride + moff(L, m) + cs * nsl + (l - m)] = acc;
+        vbase[(int64_t)(map0 + k) * vstride + cs * nsl + (l - m)] = acc;
     }
   }
 }
@@ -400,15 +470,19 @@ __device__ __forceinline__ void adjoint_body(const LegArgs& a, int m, int tile, 
 template <int NM, int R, bool SQ>
 __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                      int64_t pstride, double* __restrict__ vpart,
-                                                     int64_t vstride, int64_t tstride) {
-  __shared__ AdjShared<NM> sh;
-  const int m = blockIdx.x;
-  const int tile = blockIdx.y;
-  const int map0 = blockIdx.z * NM;
+                                                     int64_t vstride, int64_t tstride, int ntiles) {
+  __shared__ double wbuf[4][AdjCfg<NM>::NOUT * 65];
+  int mb, tile;
+  block_coords(ntiles, mb, tile);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = mb * 4 + wave;
+  if (m > a.lmax) return;
+  const int lane = threadIdx.x & 63;
+  const int map0 = blockIdx.y * NM;
   if (m == 0)
-    adjoint_body<NM, R, SQ, false>(a, m, tile, map0, nmaps, phase, pstride, vpart, vstride, tstride, sh);
+    adjoint_wave<NM, R, SQ, false>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
   else
-    adjoint_body<NM, R, SQ, true>(a, m, tile, map0, nmaps, phase, pstride, vpart, vstride, tstride, sh);
+    adjoint_wave<NM, R, SQ, true>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
 }
 
 // -------------------------------------------------------- hat scaling
@@ -435,69 +509,104 @@ __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+// Ring-pair groups per lane: R * NM <= 8 (registers); larger R amortises
+// the scalar coefficient loads and gives independent recurrences per lane,
+// smaller R gives more waves.  Prefer the largest R that still leaves
+// ~2 waves per SIMD.
+static int pick_r(int npairs, int L, int nm, int rmax) {
+  if (const char* e = std::getenv("CRS_LEG_R")) {
+    const int r = std::atoi(e);
+    if (r == 1 || r == 2 || r == 4) return std::min(r, rmax);
+  }
+  for (int R : {4, 2, 1}) {
+    if (R > rmax) continue;
+    const long tiles = (npairs + 64L * R - 1) / (64L * R);
+    const long waves = (long)(L + 1) * tiles;
+    if (waves >= 2048) return R;
+  }
+  return 1;
+}
+
+static int syn_nm(int nmaps) {
+  if (nmaps <= 8) return nmaps;
+  int best = 8, waste = 1 << 30;
+  for (int c : {8, 6, 4}) {
+    const int w = ((nmaps + c - 1) / c) * c - nmaps;
+    if (w < waste) { waste = w; best = c; }
+  }
+  return best;
+}
+
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s) {
   const int L = a.lmax;
-  const int ntiles = (a.npairs + 63) / 64;
+  const int nm = syn_nm(nmaps);
+  const int R = pick_r(a.npairs, L, nm, std::max(1, 4 / nm));
+  const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
-  int nm = nmaps <= 8 ? nmaps : 8;
-  if (nmaps > 8) {
-    // pick the chunk size with the least padding
-    int best = 8, waste = 1 << 30;
-    for (int c : {8, 6, 4}) {
-      int w = ((nmaps + c - 1) / c) * c - nmaps;
-      if (w < waste) { waste = w; best = c; }
-    }
-    nm = best;
-  }
   dim3 grid(nmb8 * ntiles, (nmaps + nm - 1) / nm);
   dim3 block(256);
-#define CRS_SYN(N) \
-  case N: hipLaunchKernelGGL(k_leg_synth<N>, grid, block, 0, s, a, nmaps, uhat, ustride, phase, pstride, ntiles); break;
-  switch (nm) {
-    CRS_SYN(1) CRS_SYN(2) CRS_SYN(3) CRS_SYN(4) CRS_SYN(5) CRS_SYN(6) CRS_SYN(7) CRS_SYN(8)
-    default: throw Error{CRS_EINVAL, "bad map chunk"};
-  }
+#define CRS_SYN(N, RR) \
+  if (nm == N && R == RR) { hipLaunchKernelGGL((k_leg_synth<N, RR>), grid, block, 0, s, a, nmaps, uhat, ustride, phase, pstride, ntiles); CRS_HIP(hipGetLastError()); return; }
+  CRS_SYN(1, 1) CRS_SYN(1, 2) CRS_SYN(1, 4)
+  CRS_SYN(2, 1) CRS_SYN(2, 2)
+  CRS_SYN(3, 1) CRS_SYN(4, 1) CRS_SYN(5, 1) CRS_SYN(6, 1) CRS_SYN(7, 1) CRS_SYN(8, 1)
 #undef CRS_SYN
-  CRS_HIP(hipGetLastError());
+  throw Error{CRS_EINVAL, "no synthesis kernel variant"};
 }
 
-static int adj_r(int npairs) {
-  int need = (npairs + 255) / 256;
-  if (need <= 1) return 1;
-  if (need <= 2) return 2;
-  return 4;
+static int adj_nm(int nmaps) { return nmaps >= 4 ? 4 : (nmaps >= 2 ? 2 : 1); }
+
+static int adj_tiles_nm(int npairs, int L, int nm) {
+  const int R = pick_r(npairs, L, nm, 8 / nm);
+  return (npairs + 64 * R - 1) / (64 * R);
 }
 
-int leg_adjoint_tiles(int npairs) {
-  int r = adj_r(npairs);
-  return (npairs + 256 * r - 1) / (256 * r);
+int leg_adjoint_tiles(int npairs, int L) {
+  // partial buffers are sized for the largest tile count over map chunkings
+  int t = 1;
+  for (int nm : {1, 2, 4}) t = std::max(t, adj_tiles_nm(npairs, L, nm));
+  return t;
+}
+
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
 }
 
 void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s) {
   const int L = a.lmax;
-  const int r = adj_r(a.npairs);
-  const int ntiles = leg_adjoint_tiles(a.npairs);
-  int nm = nmaps >= 4 ? 4 : (nmaps >= 2 ? 2 : 1);
-  dim3 grid(L + 1, ntiles, (nmaps + nm - 1) / nm);
-  dim3 block(256);
-#define CRS_ADJ(N, RR)                                                                          \
-  if (nm == N && r == RR) {                                                                     \
-    if (square)                                                                                 \
-      hipLaunchKernelGGL((k_leg_adjoint<N, RR, true>), grid, block, 0, s, a, nmaps, phase,      \
-                         pstride, vpart, vstride, tstride);                                     \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_leg_adjoint<N, RR, false>), grid, block, 0, s, a, nmaps, phase,     \
-                         pstride, vpart, vstride, tstride);                                     \
-    CRS_HIP(hipGetLastError());                                                                 \
-    return;                                                                                     \
+  const int nm = adj_nm(nmaps);
+  const int R = pick_r(a.npairs, L, nm, 8 / nm);
+  const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
+  const int ntiles_all = leg_adjoint_tiles(a.npairs, L);
+  if (ntiles < ntiles_all) {
+    // the consumer sums ntiles_all partial slices: clear the unused ones
+    const int64_t nz = (int64_t)(ntiles_all - ntiles) * tstride;
+    int64_t nb = (nz + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, vpart + (int64_t)ntiles * tstride, nz);
+  }
+  const int nmb = (L + 1 + 3) / 4;
+  const int nmb8 = (nmb + 7) / 8 * 8;
+  dim3 grid(nmb8 * ntiles, (nmaps + nm - 1) / nm);
+#define CRS_ADJ(N, RR)                                                                            \
+  if (nm == N && R == RR) {                                                                       \
+    if (square)                                                                                   \
+      hipLaunchKernelGGL((k_leg_adjoint<N, RR, true>), grid, dim3(256), 0, s, a, nmaps, phase,    \
+                         pstride, vpart, vstride, tstride, ntiles);                               \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_leg_adjoint<N, RR, false>), grid, dim3(256), 0, s, a, nmaps, phase,   \
+                         pstride, vpart, vstride, tstride, ntiles);                               \
+    CRS_HIP(hipGetLastError());                                                                   \
+    return;                                                                                       \
   }
   CRS_ADJ(1, 1) CRS_ADJ(1, 2) CRS_ADJ(1, 4)
   CRS_ADJ(2, 1) CRS_ADJ(2, 2) CRS_ADJ(2, 4)
-  CRS_ADJ(4, 1) CRS_ADJ(4, 2) CRS_ADJ(4, 4)
+  CRS_ADJ(4, 1) CRS_ADJ(4, 2)
 #undef CRS_ADJ
   throw Error{CRS_EINVAL, "no adjoint kernel variant"};
 }

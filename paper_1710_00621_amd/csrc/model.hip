@@ -215,12 +215,21 @@ enum { S_RHO = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_ACTIVE = 4, S_BREAK = 5, 
 
 // op 0: alpha = rho / p.q ; op 1: beta = r.z / rho, rho = r.z ; op 2: rr = sum ;
 // op 3: rho = r.z (start) ; op 4: tmp = sum
-__global__ void k_scalar(int op, const double* __restrict__ partial, int nblk, int nrhs,
-                         double* __restrict__ scal) {
-  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rhs >= nrhs) return;
-  double s = 0.0;
-  for (int i = 0; i < nblk; ++i) s += partial[(int64_t)rhs * nblk + i];
+__global__ __launch_bounds__(256) void k_scalar(int op, const double* __restrict__ partial, int nblk,
+                                                int nrhs, double* __restrict__ scal) {
+  // one block per rhs: fixed-order tree sum of the block partials
+  __shared__ double red[256];
+  const int rhs = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) v += partial[(int64_t)rhs * nblk + i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double s = red[0];
   double* st = scal + rhs * 8;
   const bool active = st[S_ACTIVE] != 0.0;
   if (op == 0) {
@@ -549,7 +558,7 @@ void run_band_ops(crs_model m, int nrhs, const double* in, const double* coef, b
     {
       ProfScope ps(FAM_RING, ring_bytes(g.grid, g.lmax, nmaps, RING_ROUNDTRIP) +
                                  (double)g.bands.size() * g.grid->npix * 8.0, s);
-      launch_ring(ring_args(g.grid, g.lmax), RING_ROUNDTRIP, nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
+      launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
                   pinv ? g.wP.p : g.wA.p, nrhs, s);
     }
     {
@@ -610,7 +619,7 @@ void build_diag(crs_model m, hipStream_t s) {
     ph.alloc((size_t)g.pst);
     vp.alloc((size_t)g.ntiles * g.nalm);
     out.alloc((size_t)g.nalm);
-    launch_ring(ring_args(g.grid, g.lmax), RING_DIAG, 1, ph.p, g.pst, b.tau.p, nullptr, g.grid->npix, nullptr, 1, s);
+    launch_ring(g.grid, g.lmax, RING_DIAG, 1, ph.p, g.pst, b.tau.p, nullptr, g.grid->npix, nullptr, 1, s);
     launch_leg_adjoint(leg_args(g.grid, p), 1, ph.p, g.pst, vp.p, g.nalm, g.nalm, true, s);
     launch_hat_scale(p.f.p, g.lmax, 1, vp.p, g.nalm, g.ntiles, g.nalm, out.p, g.nalm, true, s);
     dg[nu].resize(g.nalm);
@@ -747,7 +756,7 @@ int crs_model_create(const crs_model_desc* d, crs_stream st, crs_model* out) {
     }
     for (auto& g : m->groups) {
       g.plan = &get_plan(g.grid, g.lmax, s);
-      g.ntiles = leg_adjoint_tiles(g.plan->npairs);
+      g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax);
       g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
       g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
       std::vector<const double*> wa, wp;
@@ -871,7 +880,7 @@ int pcg_solve(crs_model m, int precond, int nrhs, const double* b, double* x, do
     double* scal = m->scal.p;
     auto dot_to = [&](const double* a, const double* bb, int op) {
       hipLaunchKernelGGL(k_dot, vg, dim3(256), 0, s, a, bb, n, m->partial.p);
-      hipLaunchKernelGGL(k_scalar, dim3((nrhs + 63) / 64), dim3(64), 0, s, op, m->partial.p, nblk, nrhs, scal);
+      hipLaunchKernelGGL(k_scalar, dim3(nrhs), dim3(256), 0, s, op, m->partial.p, nblk, nrhs, scal);
     };
     std::vector<double> hs((size_t)nrhs * 8, 0.0), bb(nrhs);
     for (int i = 0; i < nrhs; ++i) hs[i * 8 + S_ACTIVE] = 1.0;
@@ -919,7 +928,7 @@ int pcg_solve(crs_model m, int precond, int nrhs, const double* b, double* x, do
       op_apply(m, OP_A, nrhs, m->p.p, m->q.p, s);
       dot_to(m->p.p, m->q.p, 0);
       hipLaunchKernelGGL(k_update_xr, vg, dim3(256), 0, s, x, m->r.p, m->p.p, m->q.p, n, scal, m->partial.p);
-      hipLaunchKernelGGL(k_scalar, dim3((nrhs + 63) / 64), dim3(64), 0, s, 2, m->partial.p, nblk, nrhs, scal);
+      hipLaunchKernelGGL(k_scalar, dim3(nrhs), dim3(256), 0, s, 2, m->partial.p, nblk, nrhs, scal);
       CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       CRS_HIP(hipStreamSynchronize(s));
       bool cand = false;
@@ -1019,7 +1028,7 @@ int build_rhs(crs_model m, int nrhs, const double* const* d, const double* const
                            m->bands[nu].tau.p, dv, wv, npix);
       }
       CRS_HIP(hipGetLastError());
-      launch_ring(ring_args(g.grid, g.lmax), RING_ADJOINT, nmaps, g.phase.p, g.pst, g.pix.p, nullptr, npix,
+      launch_ring(g.grid, g.lmax, RING_ADJOINT, nmaps, g.phase.p, g.pst, g.pix.p, nullptr, npix,
                   nullptr, 1, s);
       launch_leg_adjoint(leg_args(g.grid, *g.plan), nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
                          (int64_t)nmaps * g.nalm, false, s);
@@ -1045,7 +1054,7 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
                          m->cA.p, m->nbands, g.bandids.p, g.lmax, m->ftab.p, m->Lmax, g.uhat.p, g.nalm);
       CRS_HIP(hipGetLastError());
       launch_leg_synth(leg_args(g.grid, *g.plan), nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
-      launch_ring(ring_args(g.grid, g.lmax), RING_SYNTH, nmaps, g.phase.p, g.pst, nullptr, g.pix.p, npix,
+      launch_ring(g.grid, g.lmax, RING_SYNTH, nmaps, g.phase.p, g.pst, nullptr, g.pix.p, npix,
                   nullptr, 1, s);
       for (size_t gi = 0; gi < g.bands.size(); ++gi)
         CRS_HIP(hipMemcpyAsync(maps[g.bands[gi]], g.pix.p + (int64_t)gi * nrhs * npix,
