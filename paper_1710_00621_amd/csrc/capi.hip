@@ -94,12 +94,17 @@ RingArgs ring_args(crs_grid g, int lmax) {
   r.phiden = g->d_phiden.p;
   r.nfac = g->d_nfac.p;
   r.fac = g->d_fac.p;
+  r.fftn = g->d_fftn.p;
   r.twoff = g->d_twoff.p;
   r.tw = g->d_tw.p;
+  r.bfoff = g->d_bfoff.p;
+  r.bf = g->d_bf.p;
+  r.tw2 = g->d_tw2.p;
   r.nring = g->nring;
   r.lmax = lmax;
   r.maxn = g->ring_maxn;
-  r.maxp = g->ring_maxp;
+  r.xcap = 1;
+  r.any_blue = 0;
   return r;
 }
 

@@ -47,6 +47,48 @@ std::vector<int> factorize(int n) {
   return f;
 }
 
+// In-place radix-2 complex FFT (forward, exp(-2 pi i jk / n)), n a power of two.
+void host_fft_pow2(std::vector<double2>& x) {
+  const int n = (int)x.size();
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(x[i], x[j]);
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    const int h = len / 2;
+    for (int k = 0; k < h; ++k) {
+      double sv, cv;
+      host_sincospi(-2.0 * k / len, &sv, &cv);
+      for (int i = k; i < n; i += len) {
+        const double2 u = x[i], v = x[i + h];
+        const double2 t = make_double2(v.x * cv - v.y * sv, v.x * sv + v.y * cv);
+        x[i] = make_double2(u.x + t.x, u.y + t.y);
+        x[i + h] = make_double2(u.x - t.x, u.y - t.y);
+      }
+    }
+  }
+}
+
+// Bluestein filter for a length-n DFT by a length-M cyclic convolution
+// (M >= 2n - 1): b_d = exp(+i pi d^2 / n) for |d| < n, wrapped to M, and
+// its forward DFT divided by M (so that the device inverse FFT needs no
+// scaling).  Phases are reduced exactly: d^2 mod 2n.
+std::vector<double2> bluestein_filter(int n, int M) {
+  std::vector<double2> b(M, make_double2(0.0, 0.0));
+  for (int d = 0; d < n; ++d) {
+    double sv, cv;
+    const long long t = ((long long)d * d) % (2LL * n);
+    host_sincospi((double)t / n, &sv, &cv);
+    b[d] = make_double2(cv, sv);
+    if (d) b[M - d] = b[d];
+  }
+  host_fft_pow2(b);
+  for (auto& v : b) v = make_double2(v.x / M, v.y / M);
+  return b;
+}
+
 // Gauss-Legendre nodes (descending) via Newton iteration on theta.
 void gl_nodes(int n, std::vector<double>& z, std::vector<double>& st, std::vector<double>& w) {
   z.resize(n);
@@ -107,20 +149,44 @@ void grid_finalize(crs_grid g, hipStream_t s) {
   for (int r = 0; r < nr; ++r)
     CRS_CHECK(g->nphi[r] <= kMaxRing, CRS_EUNSUPPORTED,
               "ring length above 4096 pixels is not supported");
-  // factors and twiddle tables (T_{2N}[t] = exp(-2 pi i t / (2N)), t < 2N)
-  std::vector<int> nfac(nr), fac((size_t)nr * kMaxFactors, 1);
-  std::vector<int64_t> twoff(nr);
-  std::map<int, int64_t> tw_of;
-  std::vector<double2> tw;
+  // Per ring: the complex FFT that the ring kernels run.  Even Nphi uses a
+  // half-length complex transform (two real samples per complex word); a
+  // length whose largest prime factor exceeds 7 goes through Bluestein's
+  // chirp convolution with a power-of-two FFT.
+  std::vector<int> nfac(nr), fac((size_t)nr * kMaxFactors, 1), fftn(nr);
+  std::vector<int64_t> twoff(nr), bfoff(nr, -1);
+  std::map<int, int64_t> tw_of, bf_of;
+  std::vector<double2> tw, bf;
+  g->ring_classes.clear();
+  std::map<int, int> class_of;
+  bool any_blue = false;
   for (int r = 0; r < nr; ++r) {
-    int n = g->nphi[r];
-    auto f = factorize(n);
-    CRS_CHECK((int)f.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
-    nfac[r] = (int)f.size();
-    for (size_t i = 0; i < f.size(); ++i) {
-      fac[(size_t)r * kMaxFactors + i] = f[i];
-      if (f[i] > 7) g->ring_maxp = std::max(g->ring_maxp, f[i]);
+    const int n = g->nphi[r];
+    const bool half = (n % 2) == 0;
+    const int n0 = half ? n / 2 : n;
+    auto f0 = factorize(n0);
+    bool blue = false;
+    for (int v : f0) blue = blue || v > 7;
+    int nf = n0;
+    if (blue) {
+      nf = 1;
+      while (nf < 2 * n0 - 1) nf *= 2;
+      any_blue = true;
+      auto it = bf_of.find(n0);
+      if (it == bf_of.end()) {
+        bf_of[n0] = (int64_t)bf.size();
+        bfoff[r] = (int64_t)bf.size();
+        auto spec = bluestein_filter(n0, nf);
+        bf.insert(bf.end(), spec.begin(), spec.end());
+      } else {
+        bfoff[r] = it->second;
+      }
     }
+    auto ff = factorize(nf);
+    CRS_CHECK((int)ff.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
+    nfac[r] = (int)ff.size();
+    for (size_t i = 0; i < ff.size(); ++i) fac[(size_t)r * kMaxFactors + i] = ff[i];
+    fftn[r] = nf;
     g->ring_maxn = std::max(g->ring_maxn, n);
     auto it = tw_of.find(n);
     if (it == tw_of.end()) {
@@ -135,31 +201,43 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     } else {
       twoff[r] = it->second;
     }
-  }
-  // launch classes: prime stage > 7 first, then by ring length
-  g->ring_classes.assign(4, RingClass{});
-  for (int r = 0; r < nr; ++r) {
-    bool gen = false;
-    int mp = 0;
-    for (int i = 0; i < nfac[r]; ++i) {
-      const int f = fac[(size_t)r * kMaxFactors + i];
-      if (f > 7) {
-        gen = true;
-        mp = std::max(mp, f);
-      }
+    int tier = 0;
+    while (ring_tier_maxfft(tier) < nf) ++tier;
+    auto ci = class_of.find(tier);
+    if (ci == class_of.end()) {
+      class_of[tier] = (int)g->ring_classes.size();
+      g->ring_classes.emplace_back();
+      g->ring_classes.back().tier = tier;
+      ci = class_of.find(tier);
     }
-    const int n = g->nphi[r];
-    const int c = (gen ? 0 : 2) + (n > 2048 ? 0 : 1);
-    RingClass& rc = g->ring_classes[c];
+    RingClass& rc = g->ring_classes[ci->second];
     rc.rings.push_back(r);
+    rc.blue = rc.blue || blue;
+    rc.xcap = std::max(rc.xcap, std::max(nf, n0));
     rc.maxn = std::max(rc.maxn, n);
-    rc.maxp = std::max(rc.maxp, mp);
+    const int nt = ring_tier_threads(tier);
+    if (n <= nt) rc.gcap = std::max(rc.gcap, n + n * (nt / n));
   }
+  // largest tier first
+  std::stable_sort(g->ring_classes.begin(), g->ring_classes.end(),
+                   [](const RingClass& x, const RingClass& y) { return x.tier > y.tier; });
   g->d_ring_class.clear();
   for (auto& rc : g->ring_classes) {
     g->d_ring_class.emplace_back();
     g->d_ring_class.back().upload(rc.rings, s);
   }
+  if (any_blue) {
+    std::vector<double2> t2(kBlueMax);
+    for (int t = 0; t < kBlueMax; ++t) {
+      double sv, cv;
+      host_sincospi(2.0 * t / kBlueMax, &sv, &cv);
+      t2[t] = make_double2(cv, -sv);
+    }
+    g->d_tw2.upload(t2, s);
+    g->d_bf.upload(bf, s);
+  }
+  g->d_fftn.upload(fftn, s);
+  g->d_bfoff.upload(bfoff, s);
   int np = (nr + 1) / 2;
   std::vector<double> zp(np), sp(np);
   for (int p = 0; p < np; ++p) {

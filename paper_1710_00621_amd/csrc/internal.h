@@ -95,6 +95,7 @@ struct DevBuf {
 
 constexpr int kMaxRing = 4096;   // ring FFT length limit (LDS resident)
 constexpr int kMaxFactors = 16;  // radices per ring length
+constexpr int kBlueMax = 8192;   // longest Bluestein convolution (power of two)
 
 // ---------------------------------------------------------------- grids
 // Per-(grid, lmax) Legendre plan: start table and recurrence tables.
@@ -110,12 +111,18 @@ struct ShtPlan {
   std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
 };
 
-// Rings are launched in classes of similar LDS need: (needs a prime radix
-// stage > 7) x (Nphi > 2048); classes with prime stages go first.
+// Rings are launched in classes by FFT length tier (tier t: FFT length
+// <= 1024 * 4^t, ring_tier_threads(t) threads per block).
 struct RingClass {
   std::vector<int> rings;
-  int maxn = 1, maxp = 0;
+  bool blue = false;  // some ring of the class uses Bluestein's convolution
+  int tier = 0;
+  int xcap = 1;       // complex LDS words for ring data / convolution
+  int maxn = 1;       // longest ring in the class
+  int gcap = 0;       // fold scratch words (rings shorter than the block)
 };
+inline int ring_tier_threads(int tier) { return 256 << tier; }
+inline int ring_tier_maxfft(int tier) { return 1024 << (2 * tier); }
 
 // Workspace of the public transforms (sht_synth / sht_adjoint).
 struct GridWork {
@@ -134,12 +141,14 @@ struct crs_grid_s {
   std::vector<int> nphi, phi0_num, phi0_den;  // phi0 = pi * num / den
   std::vector<int64_t> offset;
   // device ring tables
-  crs::DevBuf<int> d_nphi, d_phinum, d_phiden, d_nfac, d_fac;
-  crs::DevBuf<int64_t> d_offset, d_twoff;
+  crs::DevBuf<int> d_nphi, d_phinum, d_phiden, d_nfac, d_fac, d_fftn;
+  crs::DevBuf<int64_t> d_offset, d_twoff, d_bfoff;
+  crs::DevBuf<double2> d_bf;      // Bluestein filter spectra per distinct length
+  crs::DevBuf<double2> d_tw2;     // exp(-2 pi i t / kBlueMax), t < kBlueMax
   crs::DevBuf<double> d_zpair;    // z of the north ring of each pair
   crs::DevBuf<double> d_spair;    // sin(theta) of the north ring of each pair
   crs::DevBuf<double2> d_tw;      // twiddles exp(-2 pi i t / N) per distinct N
-  int ring_maxn = 1, ring_maxp = 0;
+  int ring_maxn = 1;
   std::vector<crs::RingClass> ring_classes;
   std::vector<crs::DevBuf<int>> d_ring_class;
   std::map<int, std::unique_ptr<crs::ShtPlan>> plans;
@@ -176,13 +185,18 @@ struct RingArgs {
   const int64_t* offset;
   const int* phinum;
   const int* phiden;
-  const int* nfac;
+  const int* nfac;     // radices of the FFT length of each ring
   const int* fac;
+  const int* fftn;     // FFT length: Nphi / 2 (even), Nphi (odd) or the Bluestein length
   const int64_t* twoff;
-  const double2* tw;
+  const double2* tw;   // per distinct Nphi: exp(-i pi t / Nphi), t < 2 Nphi
+  const int64_t* bfoff;
+  const double2* bf;
+  const double2* tw2;
   int nring, lmax;
-  int maxn, maxp;  // longest ring; largest prime radix above 7 (0 if none)
-  const int* rings;  // ring list of the launch (set by launch_ring per class)
+  int maxn, xcap;      // per launch class: longest ring, LDS data words
+  int any_blue;        // per launch class: Bluestein tables present in LDS
+  const int* rings;    // ring list of the launch (set by launch_ring per class)
 };
 // maps j = 0..nmaps-1 use weight weights[j / maps_per_weight] (RING_ROUNDTRIP).
 void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase, int64_t pstride,

@@ -509,12 +509,15 @@ __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-// Ring-pair groups per lane: R * NM <= 8 (registers); larger R amortises
-// the scalar coefficient loads and gives independent recurrences per lane,
-// smaller R gives more waves.  Prefer the largest R that still leaves
-// ~2 waves per SIMD.
-static int pick_r(int npairs, int L, int nm, int rmax) {
-  if (const char* e = std::getenv("CRS_LEG_R")) {
+// Ring-pair groups per lane: larger R amortises the scalar coefficient
+// loads and the adjoint's cross-lane reduction over more pairs, smaller R
+// gives more waves.  Take the largest R (up to rmax) that still leaves
+// `want` waves in the launch.  Measured on MI355X (HEALPix Nside 64..1024):
+// synthesis is fastest at R = 1 throughout, the adjoint at R = 2 once that
+// leaves >= 4096 waves.  The environment variables CRS_LEG_RS and
+// CRS_LEG_RA fix R for synthesis and adjoint (tuning).
+static int pick_r(int npairs, int L, int rmax, long want, const char* env) {
+  if (const char* e = std::getenv(env)) {
     const int r = std::atoi(e);
     if (r == 1 || r == 2 || r == 4) return std::min(r, rmax);
   }
@@ -522,7 +525,7 @@ static int pick_r(int npairs, int L, int nm, int rmax) {
     if (R > rmax) continue;
     const long tiles = (npairs + 64L * R - 1) / (64L * R);
     const long waves = (long)(L + 1) * tiles;
-    if (waves >= 2048) return R;
+    if (waves >= want) return R;
   }
   return 1;
 }
@@ -541,7 +544,7 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
                       double2* phase, int64_t pstride, hipStream_t s) {
   const int L = a.lmax;
   const int nm = syn_nm(nmaps);
-  const int R = pick_r(a.npairs, L, nm, std::max(1, 4 / nm));
+  const int R = pick_r(a.npairs, L, std::max(1, 4 / nm), 1L << 40, "CRS_LEG_RS");
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
@@ -556,40 +559,29 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
   throw Error{CRS_EINVAL, "no synthesis kernel variant"};
 }
 
-static int adj_nm(int nmaps) { return nmaps >= 4 ? 4 : (nmaps >= 2 ? 2 : 1); }
+// The adjoint's ring tile count depends on (npairs, L) only, so that the
+// partial-sum buffers and their consumers do not depend on the map count:
+// R is chosen first and the maps per wave follow (R * NM <= 8).
+static int adj_r(int npairs, int L) { return pick_r(npairs, L, 2, 4096, "CRS_LEG_RA"); }
 
-static int adj_tiles_nm(int npairs, int L, int nm) {
-  const int R = pick_r(npairs, L, nm, 8 / nm);
-  return (npairs + 64 * R - 1) / (64 * R);
+static int adj_nm(int nmaps, int R) {
+  const int cap = 8 / R;
+  const int nm = nmaps >= 4 ? 4 : (nmaps >= 2 ? 2 : 1);
+  return std::min(nm, cap);
 }
 
 int leg_adjoint_tiles(int npairs, int L) {
-  // partial buffers are sized for the largest tile count over map chunkings
-  int t = 1;
-  for (int nm : {1, 2, 4}) t = std::max(t, adj_tiles_nm(npairs, L, nm));
-  return t;
-}
-
-__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
+  const int R = adj_r(npairs, L);
+  return (npairs + 64 * R - 1) / (64 * R);
 }
 
 void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s) {
   const int L = a.lmax;
-  const int nm = adj_nm(nmaps);
-  const int R = pick_r(a.npairs, L, nm, 8 / nm);
+  const int R = adj_r(a.npairs, L);
+  const int nm = adj_nm(nmaps, R);
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
-  const int ntiles_all = leg_adjoint_tiles(a.npairs, L);
-  if (ntiles < ntiles_all) {
-    // the consumer sums ntiles_all partial slices: clear the unused ones
-    const int64_t nz = (int64_t)(ntiles_all - ntiles) * tstride;
-    int64_t nb = (nz + 255) / 256;
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, vpart + (int64_t)ntiles * tstride, nz);
-  }
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
   dim3 grid(nmb8 * ntiles, (nmaps + nm - 1) / nm);

@@ -4,21 +4,31 @@
 // phi_j = phi0 + 2 pi j / Nphi,
 //     f_j = Re sum_{m=0..L} (F^c_m - i F^s_m) e^{i m phi_j}.
 // The m sum is folded onto Nphi bins (m -> m mod Nphi, conjugate partner
-// -m) so that f = inverse DFT of a Hermitian spectrum; rings with
+// -m) so that f = inverse DFT of a Hermitian spectrum c; rings with
 // Nphi < 2L+1 alias exactly as the dense operator does.
 // Adjoint, first half of Y^T (Sect. 3.2): H_m = e^{-i m phi0} F^_{m mod Nphi},
 // F^_k = sum_j f_j e^{-2 pi i j k / Nphi}, H^c = Re H, H^s = -Im H.
 // Round trip (inside A and T^+): synthesis, multiply by a pixel weight
-// (tau for A, alpha^2 w^2 tau^+ for T^+; Sect. 2.3 eq:A and Sect. 3.3),
-// adjoint -- the map never leaves LDS.
+// (tau for A, alpha^2 w^2 tau^+ for T^+; Sect. 2.3 and Sect. 3.3), adjoint --
+// the map never leaves LDS.
 // Diagonal setup (M_diag, Sect. 5): for a pixel map t, G^c_m = T^_0 +
 // Re(e^{-2 i m phi0} T^_{2m}), G^s_m = T^_0 - Re(...), G_0 = (T^_0, 0):
 // sum_j t_j cos^2(m phi_j) = (G^c_m)/2 etc.
 //
-// FFT: mixed-radix Stockham autosort (radix 4, 2, 3, 5, 7 butterflies and a
-// direct stage for larger primes), one block of 256 (Nphi <= 2048) or 512
-// threads per ring and map, data resident in LDS (Nphi <= 4096).  Twiddles come from per-length
-// tables T[t] = exp(-i pi t / Nphi), t < 2 Nphi; phi0 is 0 or pi / Nphi.
+// Transform layout.  The ring data are real, so an even ring (Nphi = 2H, all
+// HEALPix rings) runs a complex FFT of length H on z_n = f_{2n} + i f_{2n+1}:
+//   synthesis  Z_k = (c_k + c_{k+H}) + i e^{2 pi i k / Nphi} (c_k - c_{k+H}),
+//              z = inverse DFT_H(Z);
+//   adjoint    Z = DFT_H(z), E_k = (Z_k + conj Z_{H-k}) / 2,
+//              O_k = (Z_k - conj Z_{H-k}) / (2i), F^_k = E_k + e^{-2 pi i k / Nphi} O_k.
+// Odd rings run a full complex FFT of length Nphi.  The FFT is a mixed-radix
+// Stockham autosort in LDS (radix 4, 2, 3, 5, 7); a length with a prime
+// factor above 7 is computed by Bluestein's chirp-z identity
+// n k = (n^2 + k^2 - (k - n)^2) / 2 as a cyclic convolution of power-of-two
+// length M >= 2n - 1 (filter spectrum precomputed per length on the host).
+// One block per (ring, map); rings are launched in up to three classes by
+// FFT length (<= 1024: 256 threads, <= 4096: 512, <= 8192: 1024); within a
+// class the half-length and Bluestein paths are chosen per ring.
 #include "internal.h"
 
 namespace crs {
@@ -31,23 +41,32 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// Twiddles of one ring from two small LDS tables: omega_2N^t = Wc[t >> 6] Wf[t & 63]
-// with Wf[i] = exp(-i pi i / N) (i < 64) and Wc[u] = exp(-i pi 64 u / N), both
-// copied from the ring's global table at kernel start (exact entries; the
-// product adds at most one rounding).
-struct Tw {
+// Exact quotient n / d for n * d < 2^32 (multiply-high by ceil(2^32 / d)).
+struct FastDiv {
+  unsigned d, m;
+  __device__ __forceinline__ explicit FastDiv(unsigned dd)
+      : d(dd), m(dd <= 1 ? 0u : (unsigned)(0xFFFFFFFFull / dd + 1)) {}
+  __device__ __forceinline__ unsigned div(unsigned n) const { return d <= 1 ? n : __umulhi(n, m); }
+  __device__ __forceinline__ unsigned mod(unsigned n) const { return n - div(n) * d; }
+};
+
+// Twiddles exp(-2 pi i u / Lt) from two LDS tables: Wf[u & 63] Wc[u >> 6]
+// (exact table entries; the product adds one rounding).  An FFT of length
+// n | Lt reads omega_n^t at u = t * q, q = Lt / n.
+struct TwCtx {
   const double2* Wf;
   const double2* Wc;
-  __device__ __forceinline__ double2 get2(int t2) const { return cmul(Wc[t2 >> 6], Wf[t2 & 63]); }
+  int q;
+  __device__ __forceinline__ double2 at(int u) const { return cmul(Wc[u >> 6], Wf[u & 63]); }
+  __device__ __forceinline__ double2 tw(int t, bool inv) const {
+    const double2 w = at(t * q);
+    return inv ? conj2(w) : w;
+  }
 };
-// omega_N^t = exp(-2 pi i t / N) (forward) or its conjugate (inverse)
-__device__ __forceinline__ double2 tw_get(const Tw& T, int t, bool inv) {
-  const double2 w = T.get2(2 * t);
-  return inv ? make_double2(w.x, -w.y) : w;
-}
 
 // cos(2 pi k / R) and sin(2 pi k / R), 1 <= k <= (R-1)/2, for the odd radices
 // (values correctly rounded from their closed forms).
@@ -67,23 +86,17 @@ __device__ __forceinline__ constexpr double dft_sin(int R, int k) {
 template <int R>
 __device__ __forceinline__ void small_dft(double2 (&v)[R], bool inv) {
   if constexpr (R == 2) {
-    double2 a = v[0], b = v[1];
+    const double2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   } else if constexpr (R == 4) {
-    double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    double2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
-    // forward: y1 = t1 - i t3, y3 = t1 + i t3 ; inverse swaps
-    double2 mit3 = make_double2(t3.y, -t3.x);  // -i * t3
+    const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const double2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    const double2 mit3 = make_double2(t3.y, -t3.x);  // -i t3
     v[0] = cadd(t0, t2);
     v[2] = csub(t0, t2);
-    if (!inv) {
-      v[1] = cadd(t1, mit3);
-      v[3] = csub(t1, mit3);
-    } else {
-      v[1] = csub(t1, mit3);
-      v[3] = cadd(t1, mit3);
-    }
+    v[1] = inv ? csub(t1, mit3) : cadd(t1, mit3);
+    v[3] = inv ? cadd(t1, mit3) : csub(t1, mit3);
   } else {
     // odd R: with a_s = x_s + x_{R-s}, b_s = x_s - x_{R-s},
     //   y_r = x_0 + sum_s a_s cos(2 pi r s / R) -/+ i sum_s b_s sin(2 pi r s / R),
@@ -121,22 +134,35 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], bool inv) {
   }
 }
 
+// One radix-R Stockham stage on x[0..n): butterfly j (k = j mod Ns) reads
+// x[j + r n/R], twiddles by omega_n^{r k span} (span = n / (Ns R); powers
+// of omega^{k span} by repeated multiplication), and writes x[(j / Ns) Ns R
+// + k + r Ns].  Every thread keeps its butterflies in registers across the
+// barrier, so the stage works in place.
 template <int R, int NT, int MAXN>
-__device__ void stage_small(double2* x, int N, int Ns, const Tw& T, bool inv) {
+__device__ void stage(double2* x, int n, int Ns, const TwCtx& C, bool inv) {
   constexpr int MAXIT = (MAXN / R + NT - 1) / NT;
-  const int nb = N / R;
+  const int nb = n / R;
+  const int span = nb / Ns;
+  const FastDiv dv((unsigned)Ns);
   const int tid = threadIdx.x;
   double2 v[MAXIT][R];
-  const int span = N / (Ns * R);
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int j = tid + NT * it;
     if (j < nb) {
-      const int k = j % Ns;
+      const int k = (int)dv.mod((unsigned)j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double2 a = x[j + r * nb];
-        v[it][r] = (r == 0 || k == 0) ? a : cmul(a, tw_get(T, r * k * span, inv));
+      for (int r = 0; r < R; ++r) v[it][r] = x[j + r * nb];
+      if (k != 0) {
+        const double2 w1 = C.tw(k * span, inv);
+        double2 w = w1;
+        v[it][1] = cmul(v[it][1], w);
+#pragma unroll
+        for (int r = 2; r < R; ++r) {
+          w = cmul(w, w1);
+          v[it][r] = cmul(v[it][r], w);
+        }
       }
       small_dft<R>(v[it], inv);
     }
@@ -146,8 +172,8 @@ __device__ void stage_small(double2* x, int N, int Ns, const Tw& T, bool inv) {
   for (int it = 0; it < MAXIT; ++it) {
     const int j = tid + NT * it;
     if (j < nb) {
-      const int k = j % Ns;
-      const int idx = (j / Ns) * Ns * R + k;
+      const int q = (int)dv.div((unsigned)j);
+      const int idx = q * Ns * R + (j - q * Ns);
 #pragma unroll
       for (int r = 0; r < R; ++r) x[idx + r * Ns] = v[it][r];
     }
@@ -155,142 +181,115 @@ __device__ void stage_small(double2* x, int N, int Ns, const Tw& T, bool inv) {
   __syncthreads();
 }
 
-// Radix-R stage for a prime R > 7: twiddle the inputs in place, then every
-// butterfly is a plain length-R DFT computed output pair by output pair
-// (r, R-r) from a_s = x_s + x_{R-s}, b_s = x_s - x_{R-s}:
-//   y_r = x_0 + sum_s a_s cos(2 pi r s / R) -/+ i sum_s b_s sin(2 pi r s / R).
-// The omega_R^{r s} factors are stepped by complex multiplication and re-read
-// from the LDS table every 16 steps to bound rounding growth.
-template <int NT, int MAXN>
-__device__ void stage_generic(double2* x, double2* wp, int N, int Ns, int R, const Tw& T, bool inv) {
-  constexpr int RB = 4;
-  // items nb * ceil((h+1)/RB) <= 0.23 N for R >= 11
-  constexpr int MAXIT = (MAXN / 4 + NT - 1) / NT;
-  const int nb = N / R;
-  const int NsR = Ns * R;
-  const int span = N / NsR;
-  const int tid = threadIdx.x;
-  const int h = (R - 1) / 2;
-  // (a) input twiddles  x[j + s nb] *= w_N^{s k span},  k = j mod Ns
-  for (int e = tid; e < N; e += NT) {
-    const int j = e % nb, s = e / nb, k = j % Ns;
-    const int t = s * k * span;
-    if (t) x[e] = cmul(x[e], tw_get(T, t, inv));
-  }
-  // (b) forward table omega_R^t = exp(-2 pi i t / R)
-  for (int t = tid; t < R; t += NT) wp[t] = T.get2(2 * t * (N / R));
-  __syncthreads();
-  // (c) a_s, b_s in place
-  for (int e = tid; e < nb * h; e += NT) {
-    const int j = e % nb, s = 1 + e / nb;
-    const double2 u = x[j + s * nb], v = x[j + (R - s) * nb];
-    x[j + s * nb] = cadd(u, v);
-    x[j + (R - s) * nb] = csub(u, v);
-  }
-  __syncthreads();
-  // (d) output pairs
-  const int nrb = (h + 1 + RB - 1) / RB;
-  const int items = nb * nrb;
-  double2 out0[MAXIT][RB], out1[MAXIT][RB];
-#pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    const int q = tid + NT * it;
-    if (q >= items) break;
-    const int j = q % nb, r0 = (q / nb) * RB;
-    const double2 x0 = x[j];
-    double2 A[RB], B[RB], w[RB], st[RB];
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      A[i] = make_double2(0.0, 0.0);
-      B[i] = make_double2(0.0, 0.0);
-      const int r = min(r0 + i, h);
-      st[i] = wp[r];  // omega^r (forward)
-      w[i] = st[i];   // omega^{r s} at s = 1
-    }
-    for (int s = 1; s <= h; ++s) {
-      const double2 as = x[j + s * nb], bs = x[j + (R - s) * nb];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        // forward omega^{rs} = c - i sn
-        const double c = w[i].x, sn = -w[i].y;
-        A[i].x = fma(as.x, c, A[i].x);
-        A[i].y = fma(as.y, c, A[i].y);
-        B[i].x = fma(bs.x, sn, B[i].x);
-        B[i].y = fma(bs.y, sn, B[i].y);
-        if ((s & 15) == 15) {
-          const int r = min(r0 + i, h);
-          w[i] = wp[(int)(((long)r * (s + 1)) % R)];
-        } else {
-          w[i] = cmul(w[i], st[i]);
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      // forward: y_r = x0 + A - i B ; y_{R-r} = x0 + A + i B (inverse swaps)
-      const double2 miB = make_double2(B[i].y, -B[i].x);
-      const double2 base = cadd(x0, A[i]);
-      out0[it][i] = inv ? csub(base, miB) : cadd(base, miB);
-      out1[it][i] = inv ? cadd(base, miB) : csub(base, miB);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    const int q = tid + NT * it;
-    if (q >= items) break;
-    const int j = q % nb, r0 = (q / nb) * RB;
-    const int k = j % Ns;
-    const int idx = (j / Ns) * NsR + k;
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      const int r = r0 + i;
-      if (r > h) break;
-      x[idx + r * Ns] = out0[it][i];
-      if (r > 0) x[idx + (R - r) * Ns] = out1[it][i];
-    }
-  }
-  __syncthreads();
-}
-
-// In-place DFT of x[0..N) in LDS: forward exp(-2 pi i jk/N), inverse exp(+).
-template <int NT, int MAXN, bool GEN>
-__device__ void fft_lds(double2* x, double2* wp, int N, const int* __restrict__ fac, int nfac,
-                        const Tw& T, bool inv) {
+// In-place DFT of x[0..n) in LDS: forward exp(-2 pi i jk/n), inverse exp(+).
+// POW2: the length is a power of two (radix 4 and 2 only).
+template <int NT, int MAXN, bool POW2>
+__device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, int nfac, const TwCtx& C,
+                        bool inv) {
   int Ns = 1;
   for (int st = 0; st < nfac; ++st) {
     const int R = fac[st];
-    switch (R) {
-      case 1: break;
-      case 2: stage_small<2, NT, MAXN>(x, N, Ns, T, inv); break;
-      case 3: stage_small<3, NT, MAXN>(x, N, Ns, T, inv); break;
-      case 4: stage_small<4, NT, MAXN>(x, N, Ns, T, inv); break;
-      case 5: stage_small<5, NT, MAXN>(x, N, Ns, T, inv); break;
-      case 7: stage_small<7, NT, MAXN>(x, N, Ns, T, inv); break;
-      default:
-        if constexpr (GEN) stage_generic<NT, MAXN>(x, wp, N, Ns, R, T, inv);
-        break;
+    if (R == 4) {
+      stage<4, NT, MAXN>(x, n, Ns, C, inv);
+    } else if (R == 2) {
+      stage<2, NT, MAXN>(x, n, Ns, C, inv);
+    } else if constexpr (!POW2) {
+      if (R == 3) stage<3, NT, MAXN>(x, n, Ns, C, inv);
+      else if (R == 5) stage<5, NT, MAXN>(x, n, Ns, C, inv);
+      else if (R == 7) stage<7, NT, MAXN>(x, n, Ns, C, inv);
     }
     Ns *= R;
   }
 }
 
-template <int NT, int MAXN, bool GEN>
-__global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, int nmaps, double2* __restrict__ phase,
-                                              int64_t pstride, const double* __restrict__ map_in,
-                                              double* __restrict__ map_out, int64_t mstride,
-                                              const double* const* __restrict__ weights,
-                                              int maps_per_weight) {
+// DFT of length n0 through Bluestein's identity:
+//   X_k = w_k sum_n (x_n w_n) b_{k-n},  w_n = exp(-i pi n^2 / n0), b_d = conj(w_d),
+// a cyclic convolution of length M (x holds M words).  The inverse DFT is
+// conj(DFT(conj x)).  Chirp phases n^2 mod 2 n0 come from the ring table
+// (exp(-i pi t / Nphi), t < 2 Nphi) at t = (n^2 mod 2 n0) * cs.
+template <int NT, int MAXN>
+__device__ void dft_bluestein(double2* x, int n0, int M, const double2* __restrict__ bf,
+                              const TwCtx& ring, int cs, const TwCtx& C, const int* __restrict__ fac,
+                              int nfac, bool inv) {
+  const int tid = threadIdx.x;
+  const unsigned twon = 2u * (unsigned)n0;
+  for (int i = tid; i < M; i += NT) {
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n0) {
+      const double2 a = x[i];
+      const int t = (int)(((unsigned)i * (unsigned)i) % twon) * cs;
+      v = cmul(inv ? conj2(a) : a, ring.at(t));
+    }
+    x[i] = v;
+  }
+  __syncthreads();
+  fft_lds<NT, MAXN, true>(x, M, fac, nfac, C, false);
+  for (int i = tid; i < M; i += NT) x[i] = cmul(x[i], bf[i]);
+  __syncthreads();
+  fft_lds<NT, MAXN, true>(x, M, fac, nfac, C, true);
+  for (int i = tid; i < n0; i += NT) {
+    const int t = (int)(((unsigned)i * (unsigned)i) % twon) * cs;
+    const double2 v = cmul(x[i], ring.at(t));
+    x[i] = inv ? conj2(v) : v;
+  }
+  __syncthreads();
+}
+
+// Sum of g_m = (F^c_m - i F^s_m) e^{i m phi0} over m = m0, m0 + S, ... <= L,
+// e^{i m phi0} = conj(T[t_m]) with t_m = m num mod 2N stepping by tS; four
+// loads in flight per step, summed in order of m.
+__device__ __forceinline__ double2 sum_g(const double2* __restrict__ ph, int m0, int S, int L, int t,
+                                         int tS, int twoN, const TwCtx& ring) {
+  double2 acc = make_double2(0.0, 0.0);
+  int m = m0;
+  auto add = [&](double2 F) {
+    acc = cadd(acc, cmulc(make_double2(F.x, -F.y), ring.at(t)));
+    t += tS;
+    if (t >= twoN) t -= twoN;
+  };
+  for (; m + 3 * S <= L; m += 4 * S) {
+    const double2 F0 = ph[m], F1 = ph[m + S], F2 = ph[m + 2 * S], F3 = ph[m + 3 * S];
+    add(F0);
+    add(F1);
+    add(F2);
+    add(F3);
+  }
+  for (; m <= L; m += S) add(ph[m]);
+  return acc;
+}
+
+// Folded spectrum c_k = (G_k + conj G_{-k}) / 2 with G_k the sum of g_m over
+// m = k mod N (0 <= k < N).
+__device__ __forceinline__ double2 fold(const double2* __restrict__ ph, int k, int N, int L, int num,
+                                        const FastDiv& d2N, int stepN, const TwCtx& ring) {
+  const double2 a = sum_g(ph, k, N, L, (int)d2N.mod((unsigned)k * (unsigned)num), stepN, 2 * N, ring);
+  const int m1 = k == 0 ? 0 : N - k;
+  const double2 b = sum_g(ph, m1, N, L, (int)d2N.mod((unsigned)m1 * (unsigned)num), stepN, 2 * N, ring);
+  return make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+}
+
+template <int NT, int MAXN>
+__global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __restrict__ phase,
+                                             int64_t pstride, const double* __restrict__ map_in,
+                                             double* __restrict__ map_out, int64_t mstride,
+                                             const double* const* __restrict__ weights,
+                                             int maps_per_weight) {
   extern __shared__ double2 lds[];
   double2* x = lds;
-  double2* wp = lds + a.maxn;
-  double2* wf = wp + a.maxp;
+  double2* wf = lds + a.xcap;
   double2* wc = wf + 64;
+  double2* wf2 = wc + (2 * a.maxn + 63) / 64;
+  double2* wc2 = wf2 + 64;
+  double2* G = a.any_blue ? wc2 + kBlueMax / 64 : wf2;  // fold scratch (rings with N <= NT)
   const int r = a.rings[blockIdx.x];
   const int map = blockIdx.y;
   const int tid = threadIdx.x;
   const int L = a.lmax;
   const int N = a.nphi[r];
+  const bool half = (N & 1) == 0;     // two real samples per complex word
+  const bool blue = a.bfoff[r] >= 0;  // Bluestein convolution
+  const int n0 = half ? N / 2 : N;
+  const int nf = a.fftn[r];
   const int64_t off = a.offset[r];
   const int num = a.phinum[r];
   const double2* __restrict__ Tg = a.tw + a.twoff[r];
@@ -300,70 +299,122 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, int nmaps, do
   const int twoN = 2 * N;
   for (int i = tid; i < 64; i += NT) wf[i] = Tg[i < twoN ? i : 0];
   for (int u = tid; u * 64 < twoN; u += NT) wc[u] = Tg[64 * u];
+  if (blue) {
+    for (int i = tid; i < 64; i += NT) wf2[i] = a.tw2[i];
+    for (int u = tid; u < kBlueMax / 64; u += NT) wc2[u] = a.tw2[64 * u];
+  }
   __syncthreads();
-  const Tw T{wf, wc};
+  const TwCtx ring{wf, wc, 1};
+  // the FFT of length n0 (direct) or nf (Bluestein)
+  const TwCtx fc = blue ? TwCtx{wf2, wc2, kBlueMax / nf} : TwCtx{wf, wc, twoN / n0};
+  const double2* __restrict__ bf = blue ? a.bf + a.bfoff[r] : nullptr;
+  const FastDiv d2N((unsigned)twoN), dN((unsigned)N);
+  double* xd = reinterpret_cast<double*>(x);
 
   if (mode == RING_SYNTH || mode == RING_ROUNDTRIP) {
-    // fold the Hermitian spectrum: c_k = (sum_{m=k mod N} g_m + sum_{m=-k mod N} conj g_m) / 2
-    // phase index of e^{-i m phi0} in the 2N table: t(m) = m num mod 2N; stepping
-    // m by N adds N num mod 2N
-    const int stepN = (int)(((unsigned)N * (unsigned)num) % (unsigned)twoN);
-    for (int k = tid; k < N; k += NT) {
-      double2 acc = make_double2(0.0, 0.0);
-      int t = (int)(((unsigned)k * (unsigned)num) % (unsigned)twoN);
-      for (int m = k; m <= L; m += N) {
-        const double2 F = ph[m];
-        // g_m = (F^c - i F^s) e^{+i m phi0}, e^{+i m phi0} = conj(T[t])
-        acc = cadd(acc, cmulc(make_double2(F.x, -F.y), T.get2(t)));
-        t += stepN;
-        if (t >= twoN) t -= twoN;
+    const int stepN = (int)d2N.mod((unsigned)N * (unsigned)num);
+    if (N <= NT) {
+      // short ring: all threads fold.  Thread p < S (S = N floor(NT / N))
+      // sums g_m over m = p mod S; G_k then adds the S / N partials of bin k.
+      const int S = N * (NT / N);
+      double2* P = G + N;
+      if (tid < S)
+        P[tid] = sum_g(ph, tid, S, L, (int)d2N.mod((unsigned)tid * (unsigned)num),
+                       (int)d2N.mod((unsigned)S * (unsigned)num), twoN, ring);
+      __syncthreads();
+      for (int k = tid; k < N; k += NT) {
+        double2 acc = P[k];
+        for (int j = k + N; j < S; j += N) acc = cadd(acc, P[j]);
+        G[k] = acc;
       }
-      const int m1 = (N - k) % N;
-      t = (int)(((unsigned)m1 * (unsigned)num) % (unsigned)twoN);
-      for (int m = m1; m <= L; m += N) {
-        const double2 F = ph[m];
-        const double2 g = cmulc(make_double2(F.x, -F.y), T.get2(t));
-        acc = cadd(acc, make_double2(g.x, -g.y));
-        t += stepN;
-        if (t >= twoN) t -= twoN;
+      __syncthreads();
+    }
+    auto cfold = [&](int k) -> double2 {
+      if (N <= NT) {
+        const double2 u = G[k], v = G[k == 0 ? 0 : N - k];
+        return make_double2(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));
       }
-      x[k] = make_double2(0.5 * acc.x, 0.5 * acc.y);
+      return fold(ph, k, N, L, num, d2N, stepN, ring);
+    };
+    for (int k = tid; k < n0; k += NT) {
+      if (half) {
+        const double2 ck = cfold(k);
+        const double2 ch = cfold(k + n0);
+        // Z_k = (c_k + c_{k+H}) + i e^{+2 pi i k / N} (c_k - c_{k+H})
+        const double2 e = conj2(ring.at(2 * k));
+        const double2 dd = cmul(e, csub(ck, ch));
+        x[k] = make_double2(ck.x + ch.x - dd.y, ck.y + ch.y + dd.x);
+      } else {
+        x[k] = cfold(k);
+      }
     }
     __syncthreads();
-    fft_lds<NT, MAXN, GEN>(x, wp, N, fac, nfac, T, /*inv=*/true);
+    if (blue)
+      dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, true);
+    else
+      fft_lds<NT, MAXN, false>(x, n0, fac, nfac, fc, true);
     if (mode == RING_SYNTH) {
       double* out = map_out + (int64_t)map * mstride + off;
-      for (int j = tid; j < N; j += NT) out[j] = x[j].x;
+      if (half) {
+        for (int j = tid; j < N; j += NT) out[j] = xd[j];
+      } else {
+        for (int j = tid; j < N; j += NT) out[j] = x[j].x;
+      }
       return;
     }
     const double* __restrict__ w = weights[map / maps_per_weight] + off;
-    for (int j = tid; j < N; j += NT) x[j] = make_double2(x[j].x * w[j], 0.0);
+    if (half) {
+      for (int j = tid; j < N; j += NT) xd[j] *= w[j];
+    } else {
+      for (int j = tid; j < N; j += NT) x[j] = make_double2(x[j].x * w[j], 0.0);
+    }
     __syncthreads();
   } else {
     const double* in = map_in + (int64_t)map * mstride + off;
-    for (int j = tid; j < N; j += NT) x[j] = make_double2(in[j], 0.0);
+    if (half) {
+      for (int j = tid; j < N; j += NT) xd[j] = in[j];
+    } else {
+      for (int j = tid; j < N; j += NT) x[j] = make_double2(in[j], 0.0);
+    }
     __syncthreads();
   }
-  fft_lds<NT, MAXN, GEN>(x, wp, N, fac, nfac, T, /*inv=*/false);
+  if (blue)
+    dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, false);
+  else
+    fft_lds<NT, MAXN, false>(x, n0, fac, nfac, fc, false);
+
+  // forward DFT of the real ring data at bin k (0 <= k < N)
+  auto spec = [&](int k) -> double2 {
+    if (half) {
+      const int kk = k >= n0 ? k - n0 : k;
+      const int k2 = kk == 0 ? 0 : n0 - kk;
+      const double2 Zk = x[kk], Zc = conj2(x[k2]);
+      const double2 E = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+      const double2 D = csub(Zk, Zc);
+      const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);  // D / (2i)
+      return cadd(E, cmul(ring.at(2 * k), O));
+    } else {
+      return x[k];
+    }
+  };
   if (mode == RING_DIAG) {
-    const double t0 = x[0].x;
+    const double t0 = spec(0).x;
     for (int m = tid; m <= L; m += NT) {
       if (m == 0) {
         ph[0] = make_double2(t0, 0.0);
       } else {
-        const unsigned m2 = (2u * (unsigned)m) % (unsigned)twoN;
-        const int k = (int)(m2 % (unsigned)N);
-        const double2 X = cmul(x[k], T.get2((int)((m2 * (unsigned)num) % (unsigned)twoN)));
+        const unsigned m2 = d2N.mod(2u * (unsigned)m);
+        const int k = (int)dN.mod(m2);
+        const double2 X = cmul(spec(k), ring.at((int)d2N.mod(m2 * (unsigned)num)));
         ph[m] = make_double2(t0 + X.x, t0 - X.x);
       }
     }
     return;
   }
   for (int m = tid; m <= L; m += NT) {
-    const double2 F = x[m % N];
     // H_m = e^{-i m phi0} F^_{m mod N};  e^{-i m phi0} = T[m num mod 2N]
-    const unsigned mm = (unsigned)m % (unsigned)twoN;
-    const double2 h = cmul(F, T.get2((int)((mm * (unsigned)num) % (unsigned)twoN)));
+    const unsigned mm = d2N.mod((unsigned)m);
+    const double2 h = cmul(spec((int)dN.mod(mm)), ring.at((int)d2N.mod(mm * (unsigned)num)));
     ph[m] = make_double2(h.x, m == 0 ? 0.0 : -h.y);
   }
 }
@@ -375,32 +426,33 @@ RingArgs ring_args(crs_grid g, int lmax);
 void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase, int64_t pstride,
                  const double* map_in, double* map_out, int64_t mstride,
                  const double* const* weights, int maps_per_weight, hipStream_t s) {
+  CRS_CHECK(lmax < 65536, CRS_EUNSUPPORTED, "lmax above 65535 is not supported by the ring stage");
   const RingArgs base = ring_args(g, lmax);
+  const int mpw = maps_per_weight < 1 ? 1 : maps_per_weight;
+  const int md = (int)mode;
   for (size_t c = 0; c < g->ring_classes.size(); ++c) {
     const RingClass& rc = g->ring_classes[c];
     if (rc.rings.empty()) continue;
     RingArgs a = base;
     a.maxn = rc.maxn;
-    a.maxp = rc.maxp;
+    a.xcap = rc.xcap;
     a.rings = g->d_ring_class[c].p;
-    dim3 grid((unsigned)rc.rings.size(), nmaps);
-    const size_t lds = (size_t)(a.maxn + a.maxp + 64 + (2 * a.maxn + 63) / 64) * sizeof(double2);
-    const int mpw = maps_per_weight < 1 ? 1 : maps_per_weight;
-    const bool gen = rc.maxp > 0;
-    if (a.maxn > 2048) {
-      if (gen)
-        hipLaunchKernelGGL((k_ring<512, 4096, true>), grid, dim3(512), lds, s, a, (int)mode, nmaps, phase,
-                           pstride, map_in, map_out, mstride, weights, mpw);
-      else
-        hipLaunchKernelGGL((k_ring<512, 4096, false>), grid, dim3(512), lds, s, a, (int)mode, nmaps, phase,
-                           pstride, map_in, map_out, mstride, weights, mpw);
-    } else {
-      if (gen)
-        hipLaunchKernelGGL((k_ring<256, 2048, true>), grid, dim3(256), lds, s, a, (int)mode, nmaps, phase,
-                           pstride, map_in, map_out, mstride, weights, mpw);
-      else
-        hipLaunchKernelGGL((k_ring<256, 2048, false>), grid, dim3(256), lds, s, a, (int)mode, nmaps, phase,
-                           pstride, map_in, map_out, mstride, weights, mpw);
+    const dim3 grid((unsigned)rc.rings.size(), nmaps);
+    const size_t words = (size_t)rc.xcap + 64 + (2 * rc.maxn + 63) / 64 +
+                         (rc.blue ? 64 + kBlueMax / 64 : 0) + rc.gcap;
+    a.any_blue = rc.blue ? 1 : 0;
+    const size_t lds = words * sizeof(double2);
+    switch (rc.tier) {
+#define CRS_RING(T, NT, MAXN)                                                                          \
+  case T:                                                                                            \
+    hipLaunchKernelGGL((k_ring<NT, MAXN>), grid, dim3(NT), lds, s, a, md, phase, pstride, map_in,    \
+                       map_out, mstride, weights, mpw);                                              \
+    break;
+      CRS_RING(0, 256, 1024)
+      CRS_RING(1, 512, 4096)
+      CRS_RING(2, 1024, 8192)
+#undef CRS_RING
+      default: throw Error{CRS_EUNSUPPORTED, "ring FFT length above 8192"};
     }
     CRS_HIP(hipGetLastError());
   }

@@ -33,6 +33,10 @@ CASES = [
     (("healpix", 32), 70, 1),    # ragged: 127 rings, 64 pairs, odd L
     (("healpix", 64), 128, 9),   # several ring tiles, nmaps > 8
     (("healpix", 13), 0, 1),     # lmax = 0, odd Nside (non power-of-two rings)
+    (("healpix", 37), 90, 2),    # cap rings 4i with prime i: Bluestein lengths
+    (("gl", 5, 4093), 40, 1),    # odd prime ring length above 2048: full-length Bluestein
+    (("gl", 9, 1), 4, 1),        # one pixel per ring: everything aliases onto m = 0
+    (("gl", 7, 2046), 1100, 1),  # even length 2 * 3 * 11 * 31: half-length Bluestein
 ]
 
 
@@ -68,13 +72,16 @@ def test_grid_geometry_matches_oracle():
 
 
 def test_gl_round_trip_on_device():
-    """Y^T W Y = I on the 33 x 65 GL grid at L = 32 (Sect. 2.1)."""
+    """Y^T W Y = I on the 33 x 65 GL grid at L = 32 (Sect. 2.1).  The bound
+    allows O(10 eps L log2 M) for two Legendre sums over 33 rings and two
+    ring FFTs of length 65 = 5 * 13, which run as length-256 Bluestein
+    convolutions."""
     torch, crsolve = _setup()
     g = crsolve.Grid.gauss_legendre(33, 65)
     w = torch.tensor(g.weights(), device="cuda")
     a = torch.randn(4, sht.nalm(32), dtype=torch.float64, device="cuda")
     back = crsolve.sht_adjoint(g, 32, crsolve.sht_synth(g, 32, a) * w)
-    assert float((back - a).abs().max()) < 1e-13
+    assert float((back - a).abs().max()) < 5e-13
 
 
 def test_adjoint_identity_and_determinism():
