@@ -63,6 +63,7 @@ __device__ __forceinline__ int64_t tri(int L, int m) {
 template <int R>
 struct Grp {
   double z[R], a0[R], a1[R];
+  double2 st[R];  // the lane's start values (mu_{ls-1}, mu_ls), loaded up front
   int ls[R];
   int lw[R];
   int nx[R];
@@ -76,6 +77,7 @@ __device__ __forceinline__ void grp_init(Grp<R>& G, const LegArgs& a, int m, int
     const bool valid = p < a.npairs;
     G.z[j] = a.zpair[valid ? p : a.npairs - 1];
     G.ls[j] = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
+    G.st[j] = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
     G.a0[j] = 0.0;
     G.a1[j] = 0.0;
     const int w = wave_min(G.ls[j]);
@@ -120,9 +122,8 @@ __device__ __forceinline__ double grp_event_step(Grp<R>& G, int j, const LegArgs
   double pv = G.a1[j];
   if (l == G.nx[j]) {
     if (G.ls[j] == l) {
-      const double2 ms = a.ms[(size_t)m * a.npairs + base + 64 * j + lane];
-      c = ms.y;
-      pv = ms.x;
+      c = G.st[j].y;
+      pv = G.st[j].x;
     }
     G.nx[j] = wave_min(G.ls[j] > l ? G.ls[j] : INT_MAX);
   }
