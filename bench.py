@@ -1,18 +1,22 @@
-"""Benchmark: PCG time-to-solution per right-hand side on MI355X.
+"""Benchmark: PCG time-to-solution per right-hand side on MI355X, batched vs plain.
 
-Workload (default "multires"): the multi-resolution full-sky model -- CMB
-and a power-law foreground (L_k = 512) seen in 5 bands at 30/70/100/143/217
-GHz on HEALPix Nside 64/128/128/256/256 (L_nu = 2 Nside, Gaussian beams
-60/30/20/10/7 arcmin, lognormal noise RMS) -- Wiener filter solved with the
-pseudo-inverse preconditioner to rel.res 1e-8.  One step = one solve of the
-workload's right-hand sides from x = 0.  The block-diagonal preconditioner
-is timed beside it (the paper's comparison).  "batched" runs 64 masked
-constrained realizations of mixed resolution (use --precond diag there: the
-pseudo-inverse preconditioner alone degrades under a mask).  All inputs are
-seeded, synthetic and resident in device memory before the timed region.
+Default workload "batched": 64 constrained realizations of multi-resolution
+problems (Nside_max 64/128/256 in turn, bands at Nside_max x (1/4, 1/2, 1/2,
+1, 1) with L_nu = 2 Nside_nu, 1-3 components, a galactic cut plus 1-degree
+disks leaving sky fraction U[0.6, 0.95], lognormal noise RMS), solved to
+rel.res 1e-8.  One step = one batched solve of all 64 problems from x = 0:
+one stacked PCG whose iterations are captured hipGraphs, with every band of
+every problem sharing the transform launches of its (grid, L).  The plain
+figure solves the same 64 problems one constrained_realization call at a
+time without graphs.  Under these masks the block-diagonal preconditioner is
+the default; the pseudo-inverse preconditioner (which degrades under a mask)
+is run on a bounded sample and its iteration count reported.  The
+"multires" field is the full-sky 5-band model with pseudo-inverse vs
+block-diagonal preconditioning.  All inputs are seeded, synthetic and
+resident in device memory before the timed region.
 
-Prints one JSON line (the contract used by the round driver), with the
-Legendre kernels' roofline measured live with HIP events and the CPU
+Prints one JSON line, with the dominant Legendre kernel's roofline measured
+live with HIP events (recorded inside the captured graphs) and the CPU
 oracle's time on a bounded sample as a reported baseline.
 
     python bench.py [--steps K] [--warmup W] [--workload batched|multires|masked]
@@ -186,25 +190,54 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
                        f"count; extrapolated per RHS")}
 
 
+def _roofline(crsolve, ms_total):
+    fam = {f: crsolve.kernel_stats(f) for f in ("legendre_synth", "legendre_adjoint", "ring_fft")}
+    dom = max(("legendre_synth", "legendre_adjoint"), key=lambda f: fam[f]["ms"])
+    st = fam[dom]
+    achieved = st["work"] / max(1e-30, st["ms"] * 1e-3) / 1e12
+    ring = fam["ring_fft"]
+    return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "avg_launch_ms": st["ms"] / max(1, st["launches"]), "launches": st["launches"],
+            "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
+            / max(1e-9, ms_total),
+            "ring_fft": {"GB/s": ring["work"] / max(1e-30, ring["ms"] * 1e-3) / 1e9,
+                         "frac_hbm": ring["work"] / max(1e-30, ring["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "share_of_step": ring["ms"] / max(1e-9, ms_total)}}
+
+
+def batch_solve(batch, probs, precond, rtol, maxiter, use_graph=True):
+    d = [[t[0] for t in p["d"]] for p in probs]
+    seeds = [p["prob"]["seed"] for p in probs]
+    xs, info = batch.solve(d=d, seeds=seeds, mode="cr", precond=precond, rtol=rtol,
+                           maxiter=maxiter, use_graph=use_graph, raise_on_error=False)
+    if info["status"] != 0:
+        raise RuntimeError(f"batched solve failed: status {info['status']}")
+    return info["iters"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="multires", choices=["batched", "multires", "masked"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "multires", "masked"])
     ap.add_argument("--nprob", type=int, default=64)
-    ap.add_argument("--precond", default="pinv", choices=["pinv", "diag"])
+    ap.add_argument("--precond", default=None, choices=["pinv", "diag"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sht-roofline", action="store_true")
+    ap.add_argument("--no-multires", action="store_true")
     a = ap.parse_args()
-    if a.workload != "batched":
-        a.nprob = 1
     if a.gpus != 1:
         print("bench.py measures one GPU: every GPU box here has one MI355X and the solver does "
               "not shard across GPUs (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if a.precond is None:
+        a.precond = "diag" if a.workload == "batched" else "pinv"
+    if a.workload != "batched":
+        a.nprob = 1
 
     import torch
 
@@ -214,60 +247,108 @@ def main():
     t0 = time.time()
     probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev)
     torch.cuda.synchronize()
-    log(f"setup {time.time() - t0:.1f}s for {len(probs)} problems")
-
-    for w in range(a.warmup):
-        it = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
-        log(f"warmup {w}: iterations min/mean/max {min(it)}/{sum(it) / len(it):.1f}/{max(it)}")
-    torch.cuda.synchronize()
-    crsolve.kernel_stats_reset()
-    crsolve.set_profiling(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for k in range(a.steps):
-        iters = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    crsolve.set_profiling(False)
-    ms_per_step = (t2 - t1) * 1e3 / a.steps
+    setup_s = time.time() - t0
+    log(f"setup {setup_s:.1f}s for {len(probs)} problems")
     nrhs = len(probs)
-    per_rhs = ms_per_step / nrhs
-    log(f"timed {a.steps} steps: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+    extra = {}
 
-    compare = None
-    if a.precond == "pinv":
-        other = "diag"
+    if a.workload == "batched":
+        tb = time.time()
+        batch = crsolve.Batch([p["model"] for p in probs])
+        setup_s += time.time() - tb
+        for w in range(a.warmup):
+            it = batch_solve(batch, probs, a.precond, a.rtol, a.maxiter)
+            log(f"warmup {w}: batched iterations max {max(it)}")
+            it_p = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
         torch.cuda.synchronize()
+        crsolve.kernel_stats_reset()
+        crsolve.set_profiling(True)
+        t1 = time.perf_counter()
+        for k in range(a.steps):
+            iters = batch_solve(batch, probs, a.precond, a.rtol, a.maxiter)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        crsolve.set_profiling(False)
+        ms_per_step = (t2 - t1) * 1e3 / a.steps
+        per_rhs = ms_per_step / nrhs
+        roof = _roofline(crsolve, ms_per_step * a.steps)
+        log(f"batched: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+        # plain: the same problems one constrained_realization call at a time, no graphs
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        it_p = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+        torch.cuda.synchronize()
+        plain_rhs = (time.perf_counter() - tp) * 1e3 / nrhs
+        log(f"plain: {plain_rhs:.3f} ms/RHS")
+        mode = (f"batched: one stacked PCG over all {nrhs} problems, each iteration one captured "
+                f"hipGraph; plain = {nrhs} separate constrained_realization calls without graphs")
+        extra["plain_ms_per_rhs"] = plain_rhs
+        extra["speedup_batched_over_plain"] = plain_rhs / per_rhs
+        extra["plain_iterations_sum"] = int(sum(it_p))
+        # the pseudo-inverse preconditioner on the smallest problem (bounded)
+        if a.precond != "pinv":
+            small = min(probs, key=lambda p: p["model"].n)
+            tq = time.perf_counter()
+            x, info = small["model"].constrained_realization(
+                small["d"], small["prob"]["seed"], mode="cr", precond="pinv", rtol=a.rtol,
+                maxiter=3000, raise_on_error=False)
+            torch.cuda.synchronize()
+            extra["pinv_sample"] = {
+                "problem_n": small["model"].n, "status": info["status"], "iters": info["iters"][0],
+                "relres": info["relres"][0], "ms": (time.perf_counter() - tq) * 1e3,
+                "note": "pseudo-inverse preconditioner under a mask (tau^+ = 0 there), maxiter 3000"}
+            log(f"pinv sample: {extra['pinv_sample']}")
+    else:
+        for w in range(a.warmup):
+            it = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+            log(f"warmup {w}: iterations {it}")
+        torch.cuda.synchronize()
+        crsolve.kernel_stats_reset()
+        crsolve.set_profiling(True)
+        t1 = time.perf_counter()
+        for k in range(a.steps):
+            iters = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        crsolve.set_profiling(False)
+        ms_per_step = (t2 - t1) * 1e3 / a.steps
+        per_rhs = ms_per_step / nrhs
+        roof = _roofline(crsolve, ms_per_step * a.steps)
+        mode = "plain (one right-hand side per solve)"
+        log(f"timed {a.steps} steps: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+
+    if a.workload != "multires" and not a.no_multires:
+        mp, _ = build_workload("multires", 1, crsolve, inputs, torch, dev)
+        res = {}
+        for pc in ("pinv", "diag"):
+            solve_all(mp, pc, a.rtol, a.maxiter, torch)
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            itm = solve_all(mp, pc, a.rtol, a.maxiter, torch)
+            torch.cuda.synchronize()
+            res[pc] = {"ms_per_rhs": (time.perf_counter() - tm) * 1e3, "iterations": itm[0]}
+        res["speedup_pinv_over_diag"] = res["diag"]["ms_per_rhs"] / res["pinv"]["ms_per_rhs"]
+        extra["multires"] = res
+        log(f"multires: {res}")
+    elif a.workload == "multires":
+        other = "diag" if a.precond == "pinv" else "pinv"
         tc = time.perf_counter()
         it_o = solve_all(probs, other, a.rtol, a.maxiter, torch)
         torch.cuda.synchronize()
         t_o = (time.perf_counter() - tc) * 1e3 / len(probs)
-        compare = {"precond": other, "ms_per_rhs": t_o, "iterations_mean": sum(it_o) / len(it_o),
-                   "speedup_pinv_over_diag": t_o / per_rhs}
-        log(f"diag: {t_o:.3f} ms/RHS, iterations {it_o}")
-    fam = {}
-    for f in ("legendre_synth", "legendre_adjoint", "ring_fft"):
-        fam[f] = crsolve.kernel_stats(f)
-    dom = max(("legendre_synth", "legendre_adjoint"), key=lambda f: fam[f]["ms"])
-    st = fam[dom]
-    avg_ms = st["ms"] / max(1, st["launches"])
-    achieved = st["work"] / max(1e-30, st["ms"] * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-            "avg_launch_ms": avg_ms, "launches": st["launches"],
-            "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
-            / max(1e-9, ms_per_step * a.steps)}
+        extra["preconditioner_comparison"] = {"precond": other, "ms_per_rhs": t_o,
+                                              "iterations_mean": sum(it_o) / len(it_o)}
+
     out = {
         "metric": "PCG time-to-solution/RHS at rel.res 1e-8, batched vs plain; SHT % roofline",
         "value": per_rhs, "unit": "ms/RHS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": a.workload, "problems": nrhs, "precond": a.precond,
-                   "rtol": a.rtol, "mode": "plain (one right-hand side per solve)",
+                   "rtol": a.rtol, "mode": mode, "setup_s": setup_s,
                    "iterations": {"min": min(iters), "mean": sum(iters) / len(iters),
-                                  "max": max(iters)}},
+                                  "max": max(iters)}, **extra},
         "roofline": roof,
-        "preconditioner_comparison": compare,
     }
     if not a.no_sht_roofline:
         out["sht_roofline"] = sht_roofline(crsolve, torch, dev)

@@ -192,6 +192,32 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
 int crs_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs, int64_t n, double* out,
                        crs_stream s);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent problems (models) solved together: the batch stacks
+ * their component vectors, merges the bands of all problems that share
+ * (grid, L_nu) into one group per transform launch, and advances every
+ * problem's PCG (each with its own scalars and stopping test) in lockstep.
+ * models: host array of nprob model handles; the models must outlive the
+ * batch and must not be modified while it exists.  Allocates the batch's
+ * workspaces.
+ */
+int crs_batch_create(const crs_model* models, int nprob, crs_stream s, crs_batch* out);
+int crs_batch_destroy(crs_batch b);
+/* Number of problems and total stacked vector length (host scalars). */
+int crs_batch_info(crs_batch b, int* nprob, int64_t* ntot);
+/* Wiener filter (CRS_MODE_WF) or constrained realization (CRS_MODE_CR) of
+ * every problem from x = 0.  d: host array of nprob entries, each NULL or a
+ * host array of the problem's nbands device map pointers (NULL = zero data),
+ * each npix_nu doubles.  seeds: host array of nprob Philox seeds (CR mode;
+ * problem p draws exactly the omegas of constrained_realization with seed
+ * seeds[p]).  x: host array of nprob device pointers receiving n_p doubles.
+ * iters, relres: host arrays of nprob, may be NULL.  use_graph != 0 runs each
+ * PCG iteration as one captured hipGraph (captured on the first solve with a
+ * given preconditioner and reused).  Returns as pcg_solve. */
+int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const uint64_t* seeds,
+                    int precond, double rtol, int maxiter, double* const* x, int* iters,
+                    double* relres, int use_graph, crs_stream s);
+
 /* ------------------------------------------------------------- profiling
  * With profiling on, every Legendre-stage kernel launch is bracketed by HIP
  * events on its stream; crs_kernel_stats synchronises on those events and

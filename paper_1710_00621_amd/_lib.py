@@ -77,6 +77,13 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_int, vp, c_int_p,
                                                c_double_p, vp]),
     "crs_model_project": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), vp]),
+    "crs_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]),
+    "crs_batch_destroy": (ctypes.c_int, [vp]),
+    "crs_batch_info": (ctypes.c_int, [vp, c_int_p, c_int64_p]),
+    "crs_batch_solve": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(vp)),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_int, ctypes.POINTER(vp), c_int_p,
+                                       c_double_p, ctypes.c_int, vp]),
     "crs_philox_normals": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_int64, vp, vp]),
     "crs_set_profiling": (ctypes.c_int, [ctypes.c_int]),

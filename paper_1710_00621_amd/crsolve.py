@@ -291,6 +291,67 @@ class Model:
         return x, {"status": st, "iters": list(iters), "relres": list(rel)}
 
 
+class Batch:
+    """Many models solved together (one stacked PCG, shared transform
+    launches).  The models must stay alive while the batch exists."""
+
+    def __init__(self, models):
+        self.models = list(models)
+        arr = (ctypes.c_void_p * len(self.models))(*[m._h.value for m in self.models])
+        h = ctypes.c_void_p()
+        check(lib().crs_batch_create(arr, len(self.models), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().crs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, d=None, seeds=None, mode="cr", precond="pinv", rtol=1e-8, maxiter=1000,
+              use_graph=True, raise_on_error=True):
+        """d: None or per problem None / list of per-band [npix] device tensors.
+        Returns (list of [n_p] solutions, info)."""
+        dev = torch.device("cuda")
+        npb = len(self.models)
+        keep = []
+        darr = None
+        if d is not None:
+            darr = (ctypes.POINTER(ctypes.c_void_p) * npb)()
+            for p, dl in enumerate(d):
+                if dl is None:
+                    darr[p] = None
+                    continue
+                a = (ctypes.c_void_p * self.models[p].nbands)()
+                for i, t in enumerate(dl):
+                    if t is None:
+                        a[i] = None
+                    else:
+                        t = t.contiguous()
+                        keep.append(t)
+                        a[i] = _dev_f64(t, "d")
+                keep.append(a)
+                darr[p] = ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p))
+        sarr = None
+        if seeds is not None:
+            sarr = (ctypes.c_uint64 * npb)(*[int(v) for v in seeds])
+        xs = [torch.empty(m.n, dtype=torch.float64, device=dev) for m in self.models]
+        xarr = (ctypes.c_void_p * npb)(*[x.data_ptr() for x in xs])
+        iters = (ctypes.c_int * npb)()
+        rel = (ctypes.c_double * npb)()
+        st = lib().crs_batch_solve(self._h, _lib.MODE[mode], darr, sarr, _lib.PRECOND[precond],
+                                   float(rtol), int(maxiter), xarr, iters, rel,
+                                   1 if use_graph else 0, _stream(dev))
+        if raise_on_error:
+            check(st)
+        return xs, {"status": st, "iters": list(iters), "relres": list(rel)}
+
+
 def philox_normals(seed, stream, rhs, n, device="cuda"):
     out = torch.empty(n, dtype=torch.float64, device=device)
     check(lib().crs_philox_normals(ctypes.c_uint64(seed), ctypes.c_uint64(stream),

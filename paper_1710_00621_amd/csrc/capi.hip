@@ -10,14 +10,11 @@ namespace {
 thread_local int g_last_code = CRS_OK;
 thread_local std::string g_last_msg;
 
-struct ProfRecord {
-  int family;
-  double work;
-  hipEvent_t e0, e1;
-};
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
+std::vector<ProfRecord> g_prof_captured;
+bool g_prof_in_graphs = true;  // event records inside captured graphs
 struct ProfTotals {
   int64_t launches = 0;
   double ms = 0.0;
@@ -32,6 +29,8 @@ void prof_resolve_locked() {
       g_prof_totals[r.family].launches += 1;
       g_prof_totals[r.family].ms += ms;
       g_prof_totals[r.family].work += r.work;
+    } else {
+      (void)hipGetLastError();
     }
     (void)hipEventDestroy(r.e0);
     (void)hipEventDestroy(r.e1);
@@ -50,21 +49,97 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+namespace {
+// Event record on a stream; on a capturing stream the record is added to the
+// capture graph as an explicit event-record node after the current
+// dependencies (a plain hipEventRecord is not captured by this runtime).
+bool record_event(hipEvent_t ev, hipStream_t s, bool captured) {
+  if (!captured) return hipEventRecord(ev, s) == hipSuccess;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t ndeps = 0;
+  if (hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &ndeps) != hipSuccess || !g) return false;
+  hipGraphNode_t node = nullptr;
+  if (hipGraphAddEventRecordNode(&node, g, deps, ndeps, ev) != hipSuccess) return false;
+  return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies) == hipSuccess;
+}
+}  // namespace
+
 ProfScope::ProfScope(int fam, double w, hipStream_t st) : family(fam), work(w), s(st) {
   if (!g_prof_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return;
+  captured = cs == hipStreamCaptureStatusActive;
+  if (captured && !g_prof_in_graphs) return;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
     return;
   }
-  (void)hipEventRecord(e0, s);
+  if (!record_event(e0, s, captured)) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    e0 = e1 = nullptr;
+  }
 }
 
 ProfScope::~ProfScope() {
   if (!e0) return;
-  (void)hipEventRecord(e1, s);
+  if (!record_event(e1, s, captured)) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return;
+  }
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (captured) {
+    g_prof_captured.push_back({family, work, e0, e1});
+    return;
+  }
   g_prof_pending.push_back({family, work, e0, e1});
   if (g_prof_pending.size() > 4096) prof_resolve_locked();
+}
+
+void prof_disable_in_graphs() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_in_graphs = false;
+}
+
+bool prof_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+std::vector<ProfRecord> prof_take_captured() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<ProfRecord> out;
+  out.swap(g_prof_captured);
+  return out;
+}
+
+void prof_account(const std::vector<ProfRecord>& recs) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  for (const auto& r : recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      g_prof_totals[r.family].launches += 1;
+      g_prof_totals[r.family].ms += ms;
+      g_prof_totals[r.family].work += r.work;
+    } else {
+      (void)hipGetLastError();  // keep a failed query from surfacing at a later launch check
+    }
+  }
+}
+
+void prof_release(std::vector<ProfRecord>& recs) {
+  for (auto& r : recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  recs.clear();
 }
 
 static void check_maps(int lmax, int nmaps, int64_t as, int64_t ms_, int64_t npix) {
@@ -83,6 +158,7 @@ LegArgs leg_args(crs_grid g, ShtPlan& p) {
   a.lmax = p.lmax;
   a.npairs = p.npairs;
   a.nring = g->nring;
+  a.skip = MapSkip{};
   return a;
 }
 
@@ -105,6 +181,7 @@ RingArgs ring_args(crs_grid g, int lmax) {
   r.maxn = g->ring_maxn;
   r.xcap = 1;
   r.any_blue = 0;
+  r.skip = MapSkip{};
   return r;
 }
 

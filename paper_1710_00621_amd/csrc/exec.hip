@@ -1,0 +1,751 @@
+// Operators, right-hand side and PCG on a set of independent systems.
+//
+//   A   = S^-1 + sum_nu P_nu^T N_nu^-1 P_nu       (Sect. 2.3, eq:A)
+//   P_nu = Y_nu B_nu q_{nu,k}                       (eq:P; Q~ = q I, Sect. 3.3)
+//   M_PI = U^+ T^+ (U^+)^T                          (eq:fullmodel-preconditioner)
+//   M_diag = (U^T diag(T) U)^-1                     (Sect. 5)
+//   b = sum_nu P_nu^T (tau d + tau^1/2 w1) + S^-1/2 w2
+//
+// A and M_PI share one shape: a per-l component -> band mix (k_mix_fwd),
+// one SHT round trip per band with a pixel weight (Legendre synthesis, ring
+// FFTs with the weight, Legendre adjoint), and a per-l band -> component mix
+// plus a per-l component -> component term (k_mix_back).  Every (system,
+// band) pair whose band shares (grid, L) with others is one map of a group,
+// so a group's Legendre and ring launches carry all of them at once.
+//
+// PCG (Sect. 2.3; Hestenes-Stiefel form): per system the scalars live on the
+// device (alpha, beta, rho, |r|^2, flags); the host reads them once per
+// iteration.  Each system stops when its recursive residual |r|/|b| <= rtol,
+// its true residual b - A x is then formed once, and it restarts from its
+// iterate (beta = 0) if that fails rtol.  With use_graph the iteration body
+// (M r, r.z, p update, A p, p.Ap, x/r update) is one captured hipGraph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+
+#include "model.h"
+
+namespace crs {
+
+namespace {
+
+constexpr int kDotBlocks = 256;   // fixed partition of every dot product
+constexpr int kScal = 8;          // scalars per system
+enum { S_RHO = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_ACTIVE = 4, S_BREAK = 5, S_RESTART = 6, S_TMP = 7 };
+
+// ---------------------------------------------------------------- kernels
+// uhat[map][i] = c_m f_lm sum_k coef[l][band][k] x[sys][coff_k + idx_k]
+__global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict__ sys,
+                          const ProbDev* __restrict__ probs, const SlotDev* __restrict__ slots, int usep,
+                          int Lb, double* __restrict__ uhat, int64_t nalm, const double* __restrict__ act) {
+  const int m = blockIdx.y;
+  const int map = blockIdx.z;
+  const SlotDev sl = slots[map];
+  if (act && act[kScal * sl.sys] == 0.0) return;
+  const SysDev S = sys[sl.sys];
+  const ProbDev P = probs[S.prob];
+  const double* __restrict__ coef = usep ? P.cP : P.cA;
+  const double* __restrict__ xs = x + S.off;
+  const int nsl = Lb - m + 1;
+  const int np = (m == 0) ? 1 : 2;
+  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
+    const int part = i / nsl, ll = i % nsl, l = m + ll;
+    double acc = 0.0;
+    for (int k = 0; k < P.nc; ++k) {
+      const int L = P.lk[k];
+      if (l > L) continue;
+      const double c = coef[((int64_t)l * P.nb + sl.band) * P.nc + k];
+      const int64_t idx = P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      acc = fma(c, xs[idx], acc);
+    }
+    uhat[(int64_t)map * nalm + moff_h(Lb, m) + i] = cm * P.ftab[tri_h(P.Lf, m) + ll] * acc;
+  }
+}
+
+// y[sys][coff_k + idx] = diag term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
+// dmode 0: no diag term; 1: (dsqrt ? C^-1/2 : C^-1) din; 2: Pi_l din.
+__global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ din,
+                           const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
+                           const int2* __restrict__ rows, int dmode, int dsqrt, int usep,
+                           const double* __restrict__ act) {
+  const int m = blockIdx.y;
+  const int2 row = rows[blockIdx.z];
+  if (act && act[kScal * row.x] == 0.0) return;
+  const SysDev S = sys[row.x];
+  const ProbDev P = probs[S.prob];
+  const int k = row.y;
+  const int Lk = P.lk[k];
+  if (m > Lk) return;
+  const int nc = P.nc;
+  const double* __restrict__ coef = usep ? P.cP : P.cA;
+  const double* __restrict__ ds = din ? din + S.off : nullptr;
+  const int nsl = Lk - m + 1;
+  const int np = (m == 0) ? 1 : 2;
+  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
+    const int part = i / nsl, ll = i % nsl, l = m + ll;
+    double acc = 0.0;
+    if (dmode == 1) {
+      const double* dt = dsqrt ? P.dSqrt : P.dInv;
+      acc = dt[(int64_t)l * nc + k] * ds[P.coff[k] + moff_h(Lk, m) + i];
+    } else if (dmode == 2) {
+      for (int kp = 0; kp < nc; ++kp) {
+        const int Lp = P.lk[kp];
+        if (l > Lp) continue;
+        acc = fma(P.dPi[((int64_t)l * nc + k) * nc + kp],
+                  ds[P.coff[kp] + moff_h(Lp, m) + (int64_t)part * (Lp - m + 1) + ll], acc);
+      }
+    }
+    const double fs = cm * P.ftab[tri_h(P.Lf, m) + ll];
+    for (int nu = 0; nu < P.nb; ++nu) {
+      const int* bi = P.binfo + 5 * nu;
+      const int L = bi[0];
+      if (l > L) continue;
+      const int gmaps = bi[1], map = bi[2] + S.rhs * bi[4], nt = bi[3];
+      const int64_t nalm = (int64_t)(L + 1) * (L + 1);
+      const int64_t tstride = (int64_t)gmaps * nalm;
+      const double* v = P.vptr[nu] + (int64_t)map * nalm + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      double s = 0.0;
+      for (int t = 0; t < nt; ++t) s += v[t * tstride];
+      acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, s, acc);
+    }
+    y[S.off + P.coff[k] + moff_h(Lk, m) + i] = acc;
+  }
+}
+
+// z[sys][coff_k + idx] = sum_k' Dinv[u][k][k'] r[sys][coff_k' + idx'] over active k'
+__global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ z,
+                             const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs) {
+  const int m = blockIdx.y;
+  const SysDev S = sys[blockIdx.z];
+  const ProbDev P = probs[S.prob];
+  const int Lc = P.Lc, nc = P.nc;
+  if (m > Lc) return;
+  const int nsl = Lc - m + 1;
+  const int np = (m == 0) ? 1 : 2;
+  const double* rs = r + S.off;
+  double* zs = z + S.off;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
+    const int part = i / nsl, ll = i % nsl, l = m + ll;
+    const int64_t u = moff_h(Lc, m) + i;
+    double rv[8];
+    for (int k = 0; k < nc; ++k) {
+      const int L = P.lk[k];
+      rv[k] = (l <= L) ? rs[P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] : 0.0;
+    }
+    for (int k = 0; k < nc; ++k) {
+      const int L = P.lk[k];
+      if (l > L) continue;
+      double acc = 0.0;
+      for (int kp = 0; kp < nc; ++kp) acc = fma(P.Dinv[(u * nc + k) * nc + kp], rv[kp], acc);
+      zs[P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] = acc;
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum256(double acc, double* red) {
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// partial[sys][blk] = this block's slice of a . b (grid: kDotBlocks x nsys)
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                             const SysDev* __restrict__ sys, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const SysDev S = sys[blockIdx.y];
+  const double* pa = a + S.off;
+  const double* pb = b + S.off;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256)
+    acc = fma(pa[i], pb[i], acc);
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// op 0: alpha = rho / p.q ; op 1: beta = r.z / rho, rho = r.z ; op 2: rr = sum ;
+// op 3: rho = r.z (start) ; op 4: tmp = sum.   One block per system, fixed-order sum.
+__global__ __launch_bounds__(256) void k_scalar(int op, const double* __restrict__ partial, int nblk,
+                                                double* __restrict__ scal) {
+  __shared__ double red[256];
+  const int sy = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) v += partial[(int64_t)sy * nblk + i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double s = red[0];
+  double* st = scal + sy * kScal;
+  const bool active = st[S_ACTIVE] != 0.0;
+  if (op == 0) {
+    if (!active) { st[S_ALPHA] = 0.0; return; }
+    if (!(s > 0.0) || !isfinite(s)) {
+      st[S_ALPHA] = 0.0;
+      st[S_BREAK] = 1.0;
+      st[S_ACTIVE] = 0.0;
+      return;
+    }
+    st[S_ALPHA] = st[S_RHO] / s;
+  } else if (op == 1) {
+    if (!active) { st[S_BETA] = 0.0; return; }
+    if (!(s > 0.0) || !isfinite(s)) {
+      st[S_BETA] = 0.0;
+      st[S_BREAK] = 1.0;
+      st[S_ACTIVE] = 0.0;
+      return;
+    }
+    st[S_BETA] = (st[S_RESTART] != 0.0) ? 0.0 : s / st[S_RHO];
+    st[S_RESTART] = 0.0;
+    st[S_RHO] = s;
+  } else if (op == 2) {
+    st[S_RR] = s;
+  } else if (op == 3) {
+    if (!(s > 0.0) || !isfinite(s)) {
+      st[S_BREAK] = (s == 0.0) ? 0.0 : 1.0;  // r = 0: already solved
+      st[S_ACTIVE] = 0.0;
+    }
+    st[S_RHO] = s;
+  } else {
+    st[S_TMP] = s;
+  }
+}
+
+// x += alpha p ; r -= alpha q ; partial r.r
+__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   const SysDev* __restrict__ sys, const double* __restrict__ scal,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[4];
+  const SysDev S = sys[blockIdx.y];
+  const double al = scal[blockIdx.y * kScal + S_ALPHA];
+  double* px = x + S.off;
+  double* pr = r + S.off;
+  const double* pp = p + S.off;
+  const double* pq = q + S.off;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256) {
+    if (al != 0.0) {
+      px[i] = fma(al, pp[i], px[i]);
+      pr[i] = fma(-al, pq[i], pr[i]);
+    }
+    const double v = pr[i];
+    acc = fma(v, v, acc);
+  }
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// p = z + beta p (active systems only)
+__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const SysDev* __restrict__ sys,
+                           const double* __restrict__ scal) {
+  const double* st = scal + blockIdx.y * kScal;
+  if (st[S_ACTIVE] == 0.0) return;
+  const SysDev S = sys[blockIdx.y];
+  const double be = st[S_BETA];
+  double* pp = p + S.off;
+  const double* pz = z + S.off;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256)
+    pp[i] = fma(be, pp[i], pz[i]);
+}
+
+// out = a - b, or out = a (b == NULL), on the systems sel selects (sel == NULL: all)
+__global__ void k_sub_sel(double* __restrict__ out, const double* __restrict__ a, const double* __restrict__ b,
+                          const SysDev* __restrict__ sys, const int* __restrict__ sel) {
+  if (sel && !sel[blockIdx.y]) return;
+  const SysDev S = sys[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256)
+    out[S.off + i] = b ? a[S.off + i] - b[S.off + i] : a[S.off + i];
+}
+
+// f[map] = tau d + sqrt(tau) w1 (per-map pointer tables; NULL = zero)
+__global__ void k_pix_rhs(double* __restrict__ f, const double* const* __restrict__ tau,
+                          const double* const* __restrict__ d, const double* const* __restrict__ w1,
+                          int64_t npix) {
+  const int map = blockIdx.y;
+  const double* t = tau[map];
+  const double* dv = d[map];
+  const double* wv = w1[map];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)gridDim.x * 256) {
+    const double tv = t[i];
+    double v = 0.0;
+    if (dv) v = tv * dv[i];
+    if (wv) v = fma(sqrt(tv), wv[i], v);
+    f[(int64_t)map * npix + i] = v;
+  }
+}
+
+inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
+
+void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
+              const double* act = nullptr) {
+  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nrows);
+  hipLaunchKernelGGL(k_mix_back, gr, dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.rows.p, dmode, dsqrt,
+                     usep, act);
+  CRS_HIP(hipGetLastError());
+}
+
+void dot_to(Exec& e, const double* a, const double* b, int op, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, vgrid(e.nsys), dim3(256), 0, s, a, b, e.dsys.p, e.partial.p);
+  hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, op, e.partial.p, kDotBlocks, e.scal.p);
+  CRS_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+Exec::~Exec() {
+  if (graph_first) (void)hipGraphExecDestroy(graph_first);
+  if (graph_iter) (void)hipGraphExecDestroy(graph_iter);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  prof_release(prof_first);
+  prof_release(prof_iter);
+}
+
+std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s) {
+  CRS_CHECK(!models.empty() && nrhs >= 1, CRS_EINVAL, "no systems");
+  auto e = std::make_unique<Exec>();
+  e->probs = models;
+  const int np = (int)models.size();
+  int64_t off = 0;
+  for (int p = 0; p < np; ++p) {
+    const crs_model m = models[p];
+    e->Lc = std::max(e->Lc, m->Lc);
+    e->has_diag = e->has_diag && m->has_diag;
+    for (int r = 0; r < nrhs; ++r) {
+      e->hsys.push_back(SysDev{p, r, off, m->n});
+      off += m->n;
+    }
+  }
+  e->nsys = (int)e->hsys.size();
+  e->ntot = off;
+  // groups: maps (problem, band) x rhs, map = base + rhs
+  std::map<std::pair<crs_grid, int>, int> gid;
+  std::vector<std::vector<int>> bmap(np);  // per problem per band: map base
+  std::vector<std::vector<int>> bgrp(np);
+  for (int p = 0; p < np; ++p) {
+    const crs_model m = models[p];
+    bmap[p].resize(m->nbands);
+    bgrp[p].resize(m->nbands);
+    for (int nu = 0; nu < m->nbands; ++nu) {
+      const Band& b = m->bands[nu];
+      auto key = std::make_pair(b.grid, b.lmax);
+      auto it = gid.find(key);
+      if (it == gid.end()) {
+        gid[key] = (int)e->groups.size();
+        e->groups.emplace_back();
+        ExecGroup& g = e->groups.back();
+        g.grid = b.grid;
+        g.lmax = b.lmax;
+        it = gid.find(key);
+      }
+      ExecGroup& g = e->groups[it->second];
+      bgrp[p][nu] = it->second;
+      bmap[p][nu] = g.nmaps;
+      g.nmaps += nrhs;
+      for (int r = 0; r < nrhs; ++r) g.hslots.push_back(SlotDev{p * nrhs + r, nu});
+    }
+  }
+  for (auto& g : e->groups) {
+    g.plan = &get_plan(g.grid, g.lmax, s);
+    g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax);
+    g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
+    g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
+    std::vector<const double*> wa, wp, ta;
+    for (const SlotDev& sl : g.hslots) {
+      const Band& b = models[e->hsys[sl.sys].prob]->bands[sl.band];
+      wa.push_back(b.tau.p);
+      wp.push_back(b.tplus.p);
+      ta.push_back(b.tau.p);
+    }
+    g.slots.upload(g.hslots, s);
+    std::vector<int> ms;
+    for (const SlotDev& sl : g.hslots) ms.push_back(sl.sys);
+    g.mapsys.upload(ms, s);
+    g.wA.upload(wa, s);
+    g.wP.upload(wp, s);
+    g.tau.upload(ta, s);
+    g.uhat.alloc((size_t)g.nmaps * g.nalm);
+    g.phase.alloc((size_t)g.nmaps * g.pst);
+    g.vpart.alloc((size_t)g.ntiles * g.nmaps * g.nalm);
+  }
+  // per-problem device views
+  std::vector<ProbDev> pd(np);
+  e->vptr.resize(np);
+  e->binfo.resize(np);
+  for (int p = 0; p < np; ++p) {
+    const crs_model m = models[p];
+    std::vector<const double*> vp(m->nbands);
+    std::vector<int> bi(5 * m->nbands);
+    for (int nu = 0; nu < m->nbands; ++nu) {
+      const ExecGroup& g = e->groups[bgrp[p][nu]];
+      vp[nu] = g.vpart.p;
+      bi[5 * nu + 0] = g.lmax;
+      bi[5 * nu + 1] = g.nmaps;
+      bi[5 * nu + 2] = bmap[p][nu];
+      bi[5 * nu + 3] = g.ntiles;
+      bi[5 * nu + 4] = 1;
+    }
+    e->vptr[p].upload(vp, s);
+    e->binfo[p].upload(bi, s);
+    ProbDev& d = pd[p];
+    d.nc = m->ncomp;
+    d.nb = m->nbands;
+    d.Lf = m->Lmax;
+    d.Lc = m->Lc;
+    d.lk = m->d_lk.p;
+    d.coff = m->d_coff.p;
+    d.cA = m->cA.p;
+    d.cP = m->cP.p;
+    d.dInv = m->dInv.p;
+    d.dSqrt = m->dSqrt.p;
+    d.dPi = m->dPi.p;
+    d.ftab = m->ftab.p;
+    d.Dinv = m->has_diag ? m->Dinv.p : nullptr;
+    d.vptr = e->vptr[p].p;
+    d.binfo = e->binfo[p].p;
+  }
+  e->dprobs.upload(pd, s);
+  e->dsys.upload(e->hsys, s);
+  std::vector<int2> rows;
+  for (int sy = 0; sy < e->nsys; ++sy)
+    for (int k = 0; k < models[e->hsys[sy].prob]->ncomp; ++k) rows.push_back(make_int2(sy, k));
+  e->nrows = (int)rows.size();
+  e->rows.upload(rows, s);
+  const size_t nn = (size_t)e->ntot;
+  e->r.alloc(nn);
+  e->z.alloc(nn);
+  e->p.alloc(nn);
+  e->q.alloc(nn);
+  e->t.alloc(nn);
+  e->xw.alloc(nn);
+  e->partial.alloc((size_t)e->nsys * kDotBlocks);
+  e->scal.alloc((size_t)e->nsys * kScal);
+  e->dsel.alloc(e->nsys);
+  CRS_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done) {
+  const bool pinv = kind == OP_PI;
+  const double* act = skip_done ? e.scal.p + S_ACTIVE : nullptr;
+  for (auto& g : e.groups) {
+    MapSkip skip;
+    if (skip_done) {
+      skip.mapsys = g.mapsys.p;
+      skip.act = act;
+    }
+    dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, g.nmaps);
+    hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, in, e.dsys.p, e.dprobs.p, g.slots.p, pinv ? 1 : 0,
+                       g.lmax, g.uhat.p, g.nalm, act);
+    CRS_HIP(hipGetLastError());
+    LegArgs la = leg_args(g.grid, *g.plan);
+    la.skip = skip;
+    {
+      ProfScope ps(FAM_LEG_SYNTH, leg_flops(*g.plan, g.nmaps), s);
+      launch_leg_synth(la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
+    }
+    {
+      ProfScope ps(FAM_RING, ring_bytes(g.grid, g.lmax, g.nmaps, RING_ROUNDTRIP) + (double)g.nmaps * g.grid->npix * 8.0,
+                   s);
+      launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, g.nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
+                  pinv ? g.wP.p : g.wA.p, 1, s, skip);
+    }
+    {
+      ProfScope ps(FAM_LEG_ADJ, leg_flops(*g.plan, g.nmaps), s);
+      launch_leg_adjoint(la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false, s);
+    }
+  }
+  if (pinv)
+    mix_back(e, out, in, 2, 0, 1, s, act);
+  else
+    mix_back(e, out, in, 1, 0, 0, s, act);
+}
+
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s) {
+  CRS_CHECK(e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
+  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nsys);
+  hipLaunchKernelGGL(k_diag_apply, gr, dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p);
+  CRS_HIP(hipGetLastError());
+}
+
+void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
+              const std::vector<std::vector<const double*>>& w1, const double* w2, double* b,
+              hipStream_t s) {
+  for (auto& g : e.groups) {
+    const int64_t npix = g.grid->npix;
+    std::vector<const double*> dp(g.nmaps), wp(g.nmaps);
+    for (int i = 0; i < g.nmaps; ++i) {
+      const SlotDev& sl = g.hslots[i];
+      dp[i] = d.empty() ? nullptr : d[sl.sys][sl.band];
+      wp[i] = w1.empty() ? nullptr : w1[sl.sys][sl.band];
+    }
+    g.dptr.upload(dp, s);
+    g.wptr.upload(wp, s);
+    g.pix.alloc((size_t)g.nmaps * npix);
+    hipLaunchKernelGGL(k_pix_rhs, dim3(kDotBlocks, g.nmaps), dim3(256), 0, s, g.pix.p, g.tau.p, g.dptr.p,
+                       g.wptr.p, npix);
+    CRS_HIP(hipGetLastError());
+    launch_ring(g.grid, g.lmax, RING_ADJOINT, g.nmaps, g.phase.p, g.pst, g.pix.p, nullptr, npix, nullptr, 1, s);
+    launch_leg_adjoint(leg_args(g.grid, *g.plan), g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
+                       (int64_t)g.nmaps * g.nalm, false, s);
+  }
+  mix_back(e, b, w2, w2 ? 1 : 0, 1, 0, s);
+  // the pointer tables were uploaded from host temporaries: finish before they go
+  CRS_HIP(hipStreamSynchronize(s));
+}
+
+void exec_project(Exec& e, const double* x, const std::vector<std::vector<double*>>& maps, hipStream_t s) {
+  for (auto& g : e.groups) {
+    const int64_t npix = g.grid->npix;
+    g.pix.alloc((size_t)g.nmaps * npix);
+    dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, g.nmaps);
+    hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, x, e.dsys.p, e.dprobs.p, g.slots.p, 0, g.lmax, g.uhat.p,
+                       g.nalm, (const double*)nullptr);
+    CRS_HIP(hipGetLastError());
+    launch_leg_synth(leg_args(g.grid, *g.plan), g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
+    launch_ring(g.grid, g.lmax, RING_SYNTH, g.nmaps, g.phase.p, g.pst, nullptr, g.pix.p, npix, nullptr, 1, s);
+    for (int i = 0; i < g.nmaps; ++i) {
+      const SlotDev& sl = g.hslots[i];
+      CRS_HIP(hipMemcpyAsync(maps[sl.sys][sl.band], g.pix.p + (int64_t)i * npix, npix * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    }
+  }
+}
+
+namespace {
+
+void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t s, bool skip_done = false) {
+  if (precond == CRS_PRECOND_PINV) {
+    exec_apply(e, OP_PI, r, z, s, skip_done);
+  } else if (precond == CRS_PRECOND_DIAG) {
+    exec_diag(e, r, z, s);
+  } else {
+    hipLaunchKernelGGL(k_sub_sel, vgrid(e.nsys), dim3(256), 0, s, z, r, (const double*)nullptr, e.dsys.p,
+                       (const int*)nullptr);
+    CRS_HIP(hipGetLastError());
+  }
+}
+
+// second half of an iteration: z = M r, rho/beta, p = z + beta p
+void iter_precond(Exec& e, int precond, hipStream_t s) {
+  precond_apply(e, precond, e.r.p, e.z.p, s, true);
+  dot_to(e, e.r.p, e.z.p, 1, s);
+  hipLaunchKernelGGL(k_update_p, vgrid(e.nsys), dim3(256), 0, s, e.p.p, e.z.p, e.dsys.p, e.scal.p);
+  CRS_HIP(hipGetLastError());
+}
+
+// first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
+void iter_apply(Exec& e, hipStream_t s) {
+  exec_apply(e, OP_A, e.p.p, e.q.p, s, true);
+  dot_to(e, e.p.p, e.q.p, 0, s);
+  hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
+                     e.partial.p);
+  hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);
+  CRS_HIP(hipGetLastError());
+}
+
+hipGraphExec_t capture(Exec& e, hipStream_t cs, const std::function<void()>& body,
+                       std::vector<ProfRecord>& recs) {
+  (void)prof_take_captured();
+  CRS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    auto left = prof_take_captured();
+    prof_release(left);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  CRS_HIP(hipStreamEndCapture(cs, &g));
+  recs = prof_take_captured();
+  hipGraphExec_t ge = nullptr;
+  const hipError_t err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) {
+    prof_release(recs);
+    throw Error{CRS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
+  }
+  (void)e;
+  return ge;
+}
+
+}  // namespace
+
+int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,
+             double* relres, double* history, bool use_graph, hipStream_t s) {
+  CRS_CHECK(precond == CRS_PRECOND_NONE || precond == CRS_PRECOND_DIAG || precond == CRS_PRECOND_PINV,
+            CRS_EINVAL, "unknown preconditioner");
+  CRS_CHECK(precond != CRS_PRECOND_DIAG || e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
+  CRS_CHECK(rtol > 0.0 && maxiter >= 0, CRS_EINVAL, "rtol must be > 0 and maxiter >= 0");
+  const int ns = e.nsys;
+  const size_t bytes = (size_t)e.ntot * sizeof(double);
+  std::vector<double> hs((size_t)ns * kScal, 0.0), bb(ns);
+  for (int i = 0; i < ns; ++i) hs[i * kScal + S_ACTIVE] = 1.0;
+  CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // |b|^2
+  dot_to(e, b, b, 4, s);
+  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipStreamSynchronize(s));
+  std::vector<int> active(ns, 1), status(ns, 0), it_used(ns, 0), sel(ns, 0);
+  for (int i = 0; i < ns; ++i) {
+    bb[i] = hs[i * kScal + S_TMP];
+    if (!(bb[i] > 0.0)) active[i] = 0;  // b = 0: x = 0 is the solution
+  }
+  CRS_HIP(hipMemcpyAsync(e.xw.p, x, bytes, hipMemcpyDeviceToDevice, s));
+  for (int i = 0; i < ns; ++i)
+    if (!active[i]) CRS_HIP(hipMemsetAsync(e.xw.p + e.hsys[i].off, 0, e.hsys[i].n * sizeof(double), s));
+  // r = b - A x, z = M r, p = z, rho = r.z
+  exec_apply(e, OP_A, e.xw.p, e.q.p, s);
+  hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.r.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
+  precond_apply(e, precond, e.r.p, e.z.p, s);
+  CRS_HIP(hipMemcpyAsync(e.p.p, e.z.p, bytes, hipMemcpyDeviceToDevice, s));
+  for (int i = 0; i < ns; ++i) hs[i * kScal + S_ACTIVE] = active[i];
+  CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  dot_to(e, e.r.p, e.z.p, 3, s);
+  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < ns; ++i)
+    if (active[i] && hs[i * kScal + S_ACTIVE] == 0.0) {
+      active[i] = 0;
+      status[i] = hs[i * kScal + S_BREAK] != 0.0 ? 2 : 0;  // r = 0 (x0 exact) counts as converged
+    }
+  // graphs of the iteration body
+  const bool prof = prof_enabled();
+  if (use_graph) {
+    const int key = precond * 2 + (prof ? 1 : 0);
+    if (e.graph_key != key) {
+      if (e.graph_first) (void)hipGraphExecDestroy(e.graph_first);
+      if (e.graph_iter) (void)hipGraphExecDestroy(e.graph_iter);
+      e.graph_first = e.graph_iter = nullptr;
+      prof_release(e.prof_first);
+      prof_release(e.prof_iter);
+      e.graph_key = -1;
+      if (!e.cap_stream) CRS_HIP(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
+      hipStream_t cs = e.cap_stream;
+      auto build = [&] {
+        e.graph_first = capture(e, cs, [&] { iter_apply(e, cs); }, e.prof_first);
+        e.graph_iter = capture(e, cs, [&] {
+          iter_precond(e, precond, cs);
+          iter_apply(e, cs);
+        }, e.prof_iter);
+      };
+      try {
+        build();
+      } catch (const Error&) {
+        if (!prof) throw;
+        // the runtime refused event records inside the capture: capture
+        // without them (kernel timing is then unavailable inside graphs)
+        (void)hipGetLastError();
+        if (e.graph_first) (void)hipGraphExecDestroy(e.graph_first);
+        e.graph_first = nullptr;
+        prof_release(e.prof_first);
+        prof_disable_in_graphs();
+        build();
+      }
+      e.graph_key = key;
+    }
+  }
+  auto any_active = [&] {
+    for (int i = 0; i < ns; ++i)
+      if (active[i]) return true;
+    return false;
+  };
+  int it = 0;
+  while (any_active() && it < maxiter) {
+    ++it;
+    if (use_graph) {
+      CRS_HIP(hipGraphLaunch(it == 1 ? e.graph_first : e.graph_iter, s));
+    } else {
+      if (it > 1) iter_precond(e, precond, s);
+      iter_apply(e, s);
+    }
+    CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CRS_HIP(hipStreamSynchronize(s));
+    if (use_graph && prof) prof_account(it == 1 ? e.prof_first : e.prof_iter);
+    bool cand = false;
+    for (int i = 0; i < ns; ++i) {
+      sel[i] = 0;
+      if (!active[i]) continue;
+      if (hs[i * kScal + S_BREAK] != 0.0) {
+        active[i] = 0;
+        status[i] = 2;
+        it_used[i] = it;
+        continue;
+      }
+      const double rel = std::sqrt(hs[i * kScal + S_RR] / bb[i]);
+      if (history) history[(size_t)(it - 1) * ns + i] = rel;
+      it_used[i] = it;
+      if (!std::isfinite(rel)) {
+        active[i] = 0;
+        status[i] = 2;
+        continue;
+      }
+      if (rel <= rtol) {
+        sel[i] = 1;
+        cand = true;
+      }
+    }
+    if (cand) {
+      // true residual of the candidates: t = b - A x
+      exec_apply(e, OP_A, e.xw.p, e.q.p, s);
+      hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
+      dot_to(e, e.t.p, e.t.p, 4, s);
+      CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      CRS_HIP(hipStreamSynchronize(s));
+      bool restart = false;
+      for (int i = 0; i < ns; ++i) {
+        if (!sel[i]) continue;
+        if (std::sqrt(hs[i * kScal + S_TMP] / bb[i]) <= rtol) {
+          active[i] = 0;
+          status[i] = 0;
+          sel[i] = 0;
+        } else {
+          restart = true;  // keep sel[i] = 1: restart from the true residual
+        }
+      }
+      for (int i = 0; i < ns; ++i) {
+        hs[i * kScal + S_ACTIVE] = active[i];
+        hs[i * kScal + S_RESTART] = sel[i];
+      }
+      CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      if (restart) {
+        CRS_HIP(hipMemcpyAsync(e.dsel.p, sel.data(), ns * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.r.p, e.t.p, (const double*)nullptr, e.dsys.p,
+                           e.dsel.p);
+        CRS_HIP(hipGetLastError());
+      }
+      CRS_HIP(hipStreamSynchronize(s));
+    }
+  }
+  for (int i = 0; i < ns; ++i)
+    if (active[i]) status[i] = 1;  // maxiter
+  // final true residuals
+  exec_apply(e, OP_A, e.xw.p, e.q.p, s);
+  hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
+  dot_to(e, e.t.p, e.t.p, 4, s);
+  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipMemcpyAsync(x, e.xw.p, bytes, hipMemcpyDeviceToDevice, s));
+  CRS_HIP(hipStreamSynchronize(s));
+  int ret = CRS_OK;
+  for (int i = 0; i < ns; ++i) {
+    if (iters) iters[i] = it_used[i];
+    if (relres) relres[i] = bb[i] > 0 ? std::sqrt(hs[i * kScal + S_TMP] / bb[i]) : 0.0;
+    if (status[i] == 2) ret = CRS_EBREAKDOWN;
+    else if (status[i] == 1 && ret == CRS_OK) ret = CRS_ENOTCONV;
+  }
+  if (ret == CRS_EBREAKDOWN) set_error(ret, "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)");
+  if (ret == CRS_ENOTCONV) set_error(ret, "PCG reached maxiter");
+  return ret;
+}
+
+}  // namespace crs

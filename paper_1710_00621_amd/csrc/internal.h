@@ -162,12 +162,24 @@ ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s);
 
 // ------------------------------------------------------------ kernels API
 // Legendre stage.  Harmonic inputs are "hat" vectors: u^ = c_m f_lm u.
+// Optional skip of finished systems: map j is skipped when
+// act[kActStride * mapsys[j]] == 0 (both NULL: nothing is skipped).
+constexpr int kActStride = 8;
+struct MapSkip {
+  const int* mapsys = nullptr;
+  const double* act = nullptr;
+  __device__ __forceinline__ bool off(int map) const {
+    return act != nullptr && act[kActStride * mapsys[map]] == 0.0;
+  }
+};
+
 struct LegArgs {
   const double* g;        // triangle
   const int* ls;          // [L+1][npairs]
   const double2* ms;      // [L+1][npairs]
   const double* zpair;    // [npairs]
   int lmax, npairs, nring;
+  MapSkip skip;
 };
 // phase: [nmaps][nring][L+1] double2 (cos, sin parts)
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
@@ -196,27 +208,44 @@ struct RingArgs {
   int nring, lmax;
   int maxn, xcap;      // per launch class: longest ring, LDS data words
   int any_blue;        // per launch class: Bluestein tables present in LDS
+  MapSkip skip;
   const int* rings;    // ring list of the launch (set by launch_ring per class)
 };
 // maps j = 0..nmaps-1 use weight weights[j / maps_per_weight] (RING_ROUNDTRIP).
 void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase, int64_t pstride,
                  const double* map_in, double* map_out, int64_t mstride,
-                 const double* const* weights, int maps_per_weight, hipStream_t s);
+                 const double* const* weights, int maps_per_weight, hipStream_t s,
+                 MapSkip skip = MapSkip{});
 
 // Scaling between plain and hat vectors: out = c_m f_lm in (+ sum over tiles).
 void launch_hat_scale(const double* f, int lmax, int nmaps, const double* in, int64_t istride,
                       int ntiles, int64_t tstride, double* out, int64_t ostride, bool square,
                       hipStream_t s);
 
-// Profiling hooks (no-ops unless profiling is on).
+// Profiling hooks (no-ops unless profiling is on).  A scope brackets its
+// launches with HIP events on the stream.  On a stream that is being
+// captured into a graph the event records become graph nodes; the pairs are
+// then handed to the graph's owner (prof_take_captured), which accounts them
+// after every replay (prof_account) and frees them (prof_release).
+struct ProfRecord {
+  int family;
+  double work;
+  hipEvent_t e0, e1;
+};
 struct ProfScope {
   int family;
   double work;
   hipStream_t s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool captured = false;
   ProfScope(int fam, double w, hipStream_t st);
   ~ProfScope();
 };
 enum { FAM_LEG_SYNTH = 0, FAM_LEG_ADJ = 1, FAM_RING = 2, FAM_COUNT = 3 };
+bool prof_enabled();
+void prof_disable_in_graphs();  // if a graph cannot hold event records
+std::vector<ProfRecord> prof_take_captured();
+void prof_account(const std::vector<ProfRecord>& recs);
+void prof_release(std::vector<ProfRecord>& recs);
 
 }  // namespace crs

@@ -318,6 +318,11 @@ __global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const d
   const int lane = threadIdx.x & 63;
   const int base = tile * 64 * R;
   const int map0 = blockIdx.y * NM;
+  if (a.skip.act) {
+    bool any = false;
+    for (int k = 0; k < NM && map0 + k < nmaps; ++k) any = any || !a.skip.off(map0 + k);
+    if (!any) return;
+  }
   if (m == 0)
     synth_wave<NM, R, false>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
   else
@@ -480,6 +485,11 @@ __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const
   if (m > a.lmax) return;
   const int lane = threadIdx.x & 63;
   const int map0 = blockIdx.y * NM;
+  if (a.skip.act) {
+    bool any = false;
+    for (int k = 0; k < NM && map0 + k < nmaps; ++k) any = any || !a.skip.off(map0 + k);
+    if (!any) return;
+  }
   if (m == 0)
     adjoint_wave<NM, R, SQ, false>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
   else

@@ -1,0 +1,150 @@
+// Internal structures of the system solver shared by model.hip (model
+// construction and its tables), exec.hip (operators, right-hand side, PCG on
+// a set of independent systems) and batch.hip (many models in one solve).
+#pragma once
+
+#include "internal.h"
+
+namespace crs {
+
+LegArgs leg_args(crs_grid g, ShtPlan& p);
+RingArgs ring_args(crs_grid g, int lmax);
+double leg_flops(const ShtPlan& p, int nmaps);
+double ring_bytes(crs_grid g, int lmax, int nmaps, int mode);
+
+__host__ __device__ inline int64_t moff_h(int L, int m) {
+  return (m == 0) ? 0 : (int64_t)(L + 1) + 2 * ((int64_t)(m - 1) * (L + 1) - (int64_t)(m - 1) * m / 2);
+}
+__host__ __device__ inline int64_t tri_h(int L, int m) { return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2; }
+
+struct Band {
+  crs_grid grid = nullptr;
+  int lmax = 0;
+  int64_t npix = 0;
+  std::vector<double> beam, q, tau_host, w_host;
+  DevBuf<double> tau, tplus;  // tau = N^-1 diagonal; tplus = alpha^2 w^2 tau^+
+  double alpha2 = 0;
+};
+
+// ------------------------------------------------------------ execution
+// An Exec runs the operators on a set of independent systems: the right-
+// hand sides of one model, or the problems of a batch.  System s belongs to
+// problem sys[s].prob and occupies [off, off + n) of the stacked vectors.
+// Bands of all systems that share (grid, L) form one group whose Legendre
+// and ring launches carry every (system, band) pair as a map.
+
+// Device view of one problem's tables (pointers into its crs_model_s).
+struct ProbDev {
+  int nc, nb, Lf, Lc;
+  const int* lk;
+  const int64_t* coff;
+  const double* cA;      // [Lf+1][nb][nc]: b_{nu,l} q_{nu,k}
+  const double* cP;      // [Lf+1][nb][nc]: U^+ entries of the band rows
+  const double* dInv;    // [Lf+1][nc]: C^-1
+  const double* dSqrt;   // [Lf+1][nc]: C^-1/2
+  const double* dPi;     // [Lf+1][nc][nc]: U^+_pr (U^+_pr)^T
+  const double* ftab;    // f_lm triangle at Lf
+  const double* Dinv;    // [(Lc+1)^2][nc][nc] M_diag blocks (NULL without)
+  const double* const* vptr;  // per band: partial sums of its group (this Exec)
+  const int* binfo;           // per band: {L, group maps, map base, tiles, map stride}
+};
+struct SysDev {
+  int prob, rhs;
+  int64_t off, n;
+};
+struct SlotDev {  // one map of a group
+  int sys, band;
+};
+
+struct ExecGroup {
+  crs_grid grid = nullptr;
+  int lmax = 0;
+  ShtPlan* plan = nullptr;
+  int nmaps = 0, ntiles = 1;
+  int64_t nalm = 0, pst = 0;
+  std::vector<SlotDev> hslots;
+  DevBuf<SlotDev> slots;
+  DevBuf<int> mapsys;                 // per map: its system
+  DevBuf<const double*> wA, wP, tau;  // per map: tau, alpha^2 w^2 tau^+, tau
+  DevBuf<double> uhat, vpart, pix;
+  DevBuf<double2> phase;
+  DevBuf<const double*> dptr, wptr;   // per map: data / omega_1 maps (right-hand side)
+};
+
+struct Exec {
+  std::vector<crs_model> probs;   // not owned
+  std::vector<SysDev> hsys;
+  int nsys = 0;
+  int64_t ntot = 0;
+  int Lc = 0;                     // largest component band-limit
+  std::vector<ExecGroup> groups;
+  DevBuf<ProbDev> dprobs;
+  DevBuf<SysDev> dsys;
+  DevBuf<int2> rows;              // (system, component) rows of the back-mix
+  int nrows = 0;
+  std::vector<DevBuf<const double*>> vptr;
+  std::vector<DevBuf<int>> binfo;
+  bool has_diag = true;
+  // PCG workspace
+  DevBuf<double> r, z, p, q, t, partial, scal;
+  DevBuf<int> dsel;
+  DevBuf<double> xw;              // iterate (the graphs reference only Exec buffers)
+  // captured iteration graphs (keyed by preconditioner and profiling)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_first = nullptr, graph_iter = nullptr;
+  int graph_key = -1;
+  std::vector<ProfRecord> prof_first, prof_iter;  // event pairs captured in the graphs
+  ~Exec();
+};
+
+// models: the problems; nrhs right-hand sides per problem (systems are
+// problem-major).  Allocates all workspaces.
+std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s);
+
+enum OpKind { OP_A = 0, OP_PI = 1 };
+// skip_done: leave out systems whose PCG has finished (their outputs are then
+// not written); used inside the iteration.
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done = false);
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s);
+// b = sum P^T (tau d + tau^1/2 w1) + C^-1/2 w2; d, w1: per (system, band) host
+// tables of device map pointers indexed [sys][band] (NULL = zero); w2 stacked.
+void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
+              const std::vector<std::vector<const double*>>& w1, const double* w2, double* b,
+              hipStream_t s);
+// maps[sys][band] <- P_band x_sys
+void exec_project(Exec& e, const double* x, const std::vector<std::vector<double*>>& maps, hipStream_t s);
+// PCG on every system of e.  b, x stacked.  use_graph: run each iteration as
+// one captured hipGraph.
+int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,
+             double* relres, double* history, bool use_graph, hipStream_t s);
+
+void launch_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, int nrhs, int64_t n,
+                           double* out, hipStream_t s);
+void model_draw_omegas(crs_model m, int nrhs, uint64_t seed, std::vector<const double*>& w1,
+                       const double*& w2, hipStream_t s);
+
+}  // namespace crs
+
+struct crs_model_s {
+  int ncomp = 0, nbands = 0;
+  std::vector<int> lk;
+  std::vector<std::vector<double>> invcl;
+  std::vector<int64_t> coff;
+  int64_t n = 0;
+  int Lc = 0, Lmax = 0;
+  std::vector<crs::Band> bands;
+  bool has_diag = false;
+  // per-l tables
+  crs::DevBuf<double> cA, cP;        // [Lmax+1][nb][nc]
+  crs::DevBuf<double> dInv, dSqrt;   // [Lmax+1][nc] diagonal prior terms
+  crs::DevBuf<double> dPi;           // [Lmax+1][nc][nc]
+  crs::DevBuf<double> ftab;          // f_lm triangle at Lmax
+  crs::DevBuf<double> Dinv;          // [(Lc+1)^2][nc][nc]
+  crs::DevBuf<int> d_lk;
+  crs::DevBuf<int64_t> d_coff;
+  std::vector<double> upinv;         // host copy [Lmax+1][nc][nb+nc]
+  // execution state for this model alone, per right-hand-side count, and CR draws
+  std::map<int, std::unique_ptr<crs::Exec>> execs;
+  crs::DevBuf<double> om1, om2, bcr;
+  int device = 0;
+};

@@ -1,339 +1,24 @@
-// The constrained-realization system and its solver (gfx950, float64).
+// The constrained-realization model: tables, setup and the per-model entry
+// points (gfx950, float64).
 //
 //   A = S^-1 + sum_nu P_nu^T N_nu^-1 P_nu           (Sect. 2.3, eq:A)
 //   P_nu = Y_nu B_nu q_{nu,k}                        (eq:P, Q~ = q I, Sect. 3.3)
 //   M_PI = U^+ T^+ (U^+)^T                            (eq:fullmodel-preconditioner)
 //   M_diag = (U^T diag(T) U)^-1                       (Sect. 5)
-//   PCG on A x = b                                    (Sect. 2.3)
 //   b = sum_nu P_nu^T (tau d + tau^1/2 w1) + S^-1/2 w2 (Sect. 2.3)
 //
-// Both A and M_PI have the same shape: a per-l component->band mix, one SHT
-// round trip per band with a pixel weight, and a per-l band->component mix
-// plus a per-l component->component term.  Bands sharing (grid, L_nu) form
-// a group whose Legendre launches carry all of the group's bands and
-// right-hand sides as maps.
+// A model owns the per-l tables of one problem: the component -> band mix
+// b_{nu,l} q_{nu,k}, the pseudo-inverse blocks U_l^+ (Sect. 3.3), the prior
+// terms and optionally the M_diag blocks.  Operators and the solver run
+// through an Exec over the model's right-hand sides (exec.hip).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 
-#include "internal.h"
-
-namespace crs {
-LegArgs leg_args(crs_grid g, ShtPlan& p);
-RingArgs ring_args(crs_grid g, int lmax);
-double leg_flops(const ShtPlan& p, int nmaps);
-double ring_bytes(crs_grid g, int lmax, int nmaps, int mode);
-}  // namespace crs
+#include "model.h"
 
 namespace {
 using namespace crs;
-
-constexpr int kDotBlocks = 256;
-
-struct Band {
-  crs_grid grid = nullptr;
-  int lmax = 0;
-  int64_t npix = 0;
-  std::vector<double> beam, q, tau_host, w_host;
-  DevBuf<double> tau, tplus;
-  double alpha2 = 0;
-  int group = 0, gidx = 0;
-};
-
-struct Group {
-  crs_grid grid = nullptr;
-  int lmax = 0;
-  std::vector<int> bands;
-  ShtPlan* plan = nullptr;
-  int ntiles = 1;
-  int64_t nalm = 0, pst = 0;
-  DevBuf<double> uhat, vpart, pix;
-  DevBuf<double2> phase;
-  DevBuf<const double*> wA, wP;  // per band in group: tau, alpha^2 w^2 tau^+
-  DevBuf<int> bandids;
-};
-
-__host__ __device__ inline int64_t moff_h(int L, int m) {
-  return (m == 0) ? 0 : (int64_t)(L + 1) + 2 * ((int64_t)(m - 1) * (L + 1) - (int64_t)(m - 1) * m / 2);
-}
-__host__ __device__ inline int64_t tri_h(int L, int m) { return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2; }
-
-}  // namespace
-
-struct crs_model_s {
-  int ncomp = 0, nbands = 0;
-  std::vector<int> lk;
-  std::vector<std::vector<double>> invcl;
-  std::vector<int64_t> coff;
-  int64_t n = 0;
-  int Lc = 0, Lmax = 0;
-  std::vector<Band> bands;
-  std::vector<Group> groups;
-  bool has_diag = false;
-  // per-l tables
-  DevBuf<double> cA, cP;        // [Lmax+1][nb][nc]
-  DevBuf<double> dInv, dSqrt;   // [Lmax+1][nc] diagonal prior terms
-  DevBuf<double> dPi;           // [Lmax+1][nc][nc]
-  DevBuf<double> ftab;          // f_lm triangle at Lmax
-  DevBuf<double> Dinv;          // [(Lc+1)^2][nc][nc]
-  DevBuf<int> d_lk;
-  DevBuf<int64_t> d_coff;
-  // band views for the back-mix
-  DevBuf<const double*> d_vptr;
-  DevBuf<int> d_binfo;  // per band: L, gsize, gidx, ntiles
-  std::vector<double> upinv;  // host copy [Lmax+1][nc][nb+nc]
-  // workspaces
-  int nrhs_ws = 0;
-  DevBuf<double> r, z, p, q, t;
-  DevBuf<double> partial;
-  DevBuf<double> scal;  // per rhs: rho, alpha, beta, rr, bb, flags...
-  DevBuf<double> om1, om2, bcr;
-  DevBuf<int> dsel;
-  int device = 0;
-};
-
-namespace {
-
-// ---------------------------------------------------------------- kernels
-// out_hat[map][i] = c_m f_lm * sum_k coef[l][band][k] * x[rhs][coff_k + idx_k]
-__global__ void k_mix_fwd(const double* __restrict__ x, int64_t n, int nrhs, int nc,
-                          const int* __restrict__ lk, const int64_t* __restrict__ coff,
-                          const double* __restrict__ coef, int nb, const int* __restrict__ bandids,
-                          int Lb, const double* __restrict__ ftab, int Lf,
-                          double* __restrict__ uhat, int64_t nalm) {
-  const int m = blockIdx.y;
-  const int map = blockIdx.z;  // = gidx * nrhs + rhs
-  const int gidx = map / nrhs, rhs = map % nrhs;
-  const int band = bandids[gidx];
-  const int nsl = Lb - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
-    double acc = 0.0;
-    for (int k = 0; k < nc; ++k) {
-      const int L = lk[k];
-      if (l > L) continue;
-      const double c = coef[((int64_t)l * nb + band) * nc + k];
-      const int64_t idx = coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
-      acc = fma(c, x[(int64_t)rhs * n + idx], acc);
-    }
-    uhat[(int64_t)map * nalm + moff_h(Lb, m) + i] = cm * ftab[tri_h(Lf, m) + ll] * acc;
-  }
-}
-
-// y[rhs][coff_k + idx_k] = diag-term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
-// binfo per band: {L, gsize, gidx, ntiles}
-__global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ din, int64_t n, int nrhs,
-                           int nc, const int* __restrict__ lk, const int64_t* __restrict__ coff,
-                           const double* __restrict__ coef, int nb,
-                           const double* const* __restrict__ vptr, const int* __restrict__ binfo,
-                           int dmode, const double* __restrict__ dtab, const double* __restrict__ ftab,
-                           int Lf, int Lc) {
-  const int m = blockIdx.y;
-  const int k = blockIdx.z % nc;
-  const int rhs = blockIdx.z / nc;
-  const int Lk = lk[k];
-  if (m > Lk) return;
-  const int nsl = Lk - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
-    double acc = 0.0;
-    if (dmode == 1) {
-      acc = dtab[(int64_t)l * nc + k] * din[(int64_t)rhs * n + coff[k] + moff_h(Lk, m) + i];
-    } else if (dmode == 2) {
-      for (int kp = 0; kp < nc; ++kp) {
-        const int Lp = lk[kp];
-        if (l > Lp) continue;
-        acc = fma(dtab[((int64_t)l * nc + k) * nc + kp],
-                  din[(int64_t)rhs * n + coff[kp] + moff_h(Lp, m) + (int64_t)part * (Lp - m + 1) + ll], acc);
-      }
-    }
-    const double fs = cm * ftab[tri_h(Lf, m) + ll];
-    for (int nu = 0; nu < nb; ++nu) {
-      const int L = binfo[4 * nu + 0];
-      if (l > L) continue;
-      const int gsize = binfo[4 * nu + 1], gidx = binfo[4 * nu + 2], nt = binfo[4 * nu + 3];
-      const int64_t nalm = (int64_t)(L + 1) * (L + 1);
-      const int64_t tstride = (int64_t)gsize * nrhs * nalm;
-      const double* v = vptr[nu] + (int64_t)(gidx * nrhs + rhs) * nalm + moff_h(L, m) +
-                        (int64_t)part * (L - m + 1) + ll;
-      double s = 0.0;
-      for (int t = 0; t < nt; ++t) s += v[t * tstride];
-      acc = fma(coef[((int64_t)l * nb + nu) * nc + k] * fs, s, acc);
-    }
-    y[(int64_t)rhs * n + coff[k] + moff_h(Lk, m) + i] = acc;
-  }
-}
-
-// z[rhs][coff_k + idx] = sum_k' Dinv[u][k][k'] r[rhs][coff_k' + idx'] over active k'
-__global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ z, int64_t n, int nc,
-                             const int* __restrict__ lk, const int64_t* __restrict__ coff,
-                             const double* __restrict__ Dinv, int Lc) {
-  const int m = blockIdx.y;
-  const int rhs = blockIdx.z;
-  const int nsl = Lc - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
-    const int64_t u = moff_h(Lc, m) + i;
-    double rv[8];
-    for (int k = 0; k < nc; ++k) {
-      const int L = lk[k];
-      rv[k] = (l <= L) ? r[(int64_t)rhs * n + coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] : 0.0;
-    }
-    for (int k = 0; k < nc; ++k) {
-      const int L = lk[k];
-      if (l > L) continue;
-      double acc = 0.0;
-      for (int kp = 0; kp < nc; ++kp) acc = fma(Dinv[(u * nc + k) * nc + kp], rv[kp], acc);
-      z[(int64_t)rhs * n + coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] = acc;
-    }
-  }
-}
-
-// partial[rhs][blk] = sum over this block's slice of a[rhs][i] * b[rhs][i]
-__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                             int64_t n, double* __restrict__ partial) {
-  __shared__ double red[4];
-  const int rhs = blockIdx.y;
-  const double* pa = a + (int64_t)rhs * n;
-  const double* pb = b + (int64_t)rhs * n;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    acc = fma(pa[i], pb[i], acc);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[(int64_t)rhs * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// Per-rhs scalar state, layout scal[rhs * 8 + field].
-enum { S_RHO = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_ACTIVE = 4, S_BREAK = 5, S_RESTART = 6, S_TMP = 7 };
-
-// op 0: alpha = rho / p.q ; op 1: beta = r.z / rho, rho = r.z ; op 2: rr = sum ;
-// op 3: rho = r.z (start) ; op 4: tmp = sum
-__global__ __launch_bounds__(256) void k_scalar(int op, const double* __restrict__ partial, int nblk,
-                                                int nrhs, double* __restrict__ scal) {
-  // one block per rhs: fixed-order tree sum of the block partials
-  __shared__ double red[256];
-  const int rhs = blockIdx.x;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) v += partial[(int64_t)rhs * nblk + i];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double s = red[0];
-  double* st = scal + rhs * 8;
-  const bool active = st[S_ACTIVE] != 0.0;
-  if (op == 0) {
-    if (!active) { st[S_ALPHA] = 0.0; return; }
-    if (!(s > 0.0) || !isfinite(s)) {
-      st[S_ALPHA] = 0.0;
-      st[S_BREAK] = 1.0;
-      st[S_ACTIVE] = 0.0;
-      return;
-    }
-    st[S_ALPHA] = st[S_RHO] / s;
-  } else if (op == 1) {
-    if (!active) { st[S_BETA] = 0.0; return; }
-    if (!(s > 0.0) || !isfinite(s)) {
-      st[S_BETA] = 0.0;
-      st[S_BREAK] = 1.0;
-      st[S_ACTIVE] = 0.0;
-      return;
-    }
-    st[S_BETA] = (st[S_RESTART] != 0.0) ? 0.0 : s / st[S_RHO];
-    st[S_RESTART] = 0.0;
-    st[S_RHO] = s;
-  } else if (op == 2) {
-    st[S_RR] = s;
-  } else if (op == 3) {
-    if (!(s > 0.0) || !isfinite(s)) {
-      st[S_BREAK] = (s == 0.0) ? 0.0 : 1.0;  // r = 0: already solved
-      st[S_ACTIVE] = 0.0;
-    }
-    st[S_RHO] = s;
-  } else {
-    st[S_TMP] = s;
-  }
-}
-
-// x += alpha p ; r -= alpha q ; partial r.r
-__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p, const double* __restrict__ q,
-                                                   int64_t n, const double* __restrict__ scal,
-                                                   double* __restrict__ partial) {
-  __shared__ double red[4];
-  const int rhs = blockIdx.y;
-  const double al = scal[rhs * 8 + S_ALPHA];
-  double* px = x + (int64_t)rhs * n;
-  double* pr = r + (int64_t)rhs * n;
-  const double* pp = p + (int64_t)rhs * n;
-  const double* pq = q + (int64_t)rhs * n;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    if (al != 0.0) {
-      px[i] = fma(al, pp[i], px[i]);
-      pr[i] = fma(-al, pq[i], pr[i]);
-    }
-    const double v = pr[i];
-    acc = fma(v, v, acc);
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[(int64_t)rhs * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// p = z + beta p (active rhs only)
-__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t n,
-                           const double* __restrict__ scal) {
-  const int rhs = blockIdx.y;
-  const double* st = scal + rhs * 8;
-  if (st[S_ACTIVE] == 0.0) return;
-  const double be = st[S_BETA];
-  double* pp = p + (int64_t)rhs * n;
-  const double* pz = z + (int64_t)rhs * n;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    pp[i] = fma(be, pp[i], pz[i]);
-}
-
-// out = a - b (per rhs, only where mask rhs flag selects; mask == null: all)
-__global__ void k_sub(double* __restrict__ out, const double* __restrict__ a, const double* __restrict__ b,
-                      int64_t n, const int* __restrict__ sel) {
-  const int rhs = blockIdx.y;
-  if (sel && !sel[rhs]) return;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    out[(int64_t)rhs * n + i] = a[(int64_t)rhs * n + i] - b[(int64_t)rhs * n + i];
-}
-
-__global__ void k_copy_sel(double* __restrict__ out, const double* __restrict__ a, int64_t n,
-                           const int* __restrict__ sel) {
-  const int rhs = blockIdx.y;
-  if (sel && !sel[rhs]) return;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    out[(int64_t)rhs * n + i] = a[(int64_t)rhs * n + i];
-}
-
-// f = tau d + sqrt(tau) w1 for one band's maps (rhs-major)
-__global__ void k_pix_rhs(double* __restrict__ f, const double* __restrict__ tau,
-                          const double* __restrict__ d, const double* __restrict__ w1, int64_t npix) {
-  const int rhs = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)gridDim.x * 256) {
-    const double t = tau[i];
-    double v = 0.0;
-    if (d) v = t * d[(int64_t)rhs * npix + i];
-    if (w1) v = fma(sqrt(t), w1[(int64_t)rhs * npix + i], v);
-    f[(int64_t)rhs * npix + i] = v;
-  }
-}
 
 // Philox4x64-10 (Salmon et al. SC'11) and Box-Muller normals.
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
@@ -379,13 +64,6 @@ __global__ void k_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, 
     for (int i = 0; i < 4; ++i)
       if (4 * b + i < n) o[4 * b + i] = v[i];
   }
-}
-
-inline dim3 vgrid(int64_t n, int nrhs) {
-  int64_t nb = (n + 255) / 256;
-  if (nb > kDotBlocks) nb = kDotBlocks;
-  if (nb < 1) nb = 1;
-  return dim3((unsigned)nb, nrhs);
 }
 
 // ------------------------------------------------------------ host helpers
@@ -513,98 +191,6 @@ void build_mix_tables(crs_model m, hipStream_t s) {
   m->dSqrt.upload(ds, s);
 }
 
-void ensure_ws(crs_model m, int nrhs, hipStream_t s) {
-  if (nrhs <= m->nrhs_ws) return;
-  CRS_HIP(hipStreamSynchronize(s));
-  for (auto& g : m->groups) {
-    const int nmaps = (int)g.bands.size() * nrhs;
-    g.uhat.alloc((size_t)nmaps * g.nalm);
-    g.phase.alloc((size_t)nmaps * g.pst);
-    g.vpart.alloc((size_t)g.ntiles * nmaps * g.nalm);
-  }
-  std::vector<const double*> vp(m->nbands);
-  for (int nu = 0; nu < m->nbands; ++nu) vp[nu] = m->groups[m->bands[nu].group].vpart.p;
-  m->d_vptr.upload(vp, s);
-  const size_t nn = (size_t)nrhs * m->n;
-  m->r.alloc(nn);
-  m->z.alloc(nn);
-  m->p.alloc(nn);
-  m->q.alloc(nn);
-  m->t.alloc(nn);
-  m->partial.alloc((size_t)nrhs * kDotBlocks);
-  m->scal.alloc((size_t)nrhs * 8);
-  m->dsel.alloc(nrhs);
-  CRS_HIP(hipStreamSynchronize(s));
-  m->nrhs_ws = nrhs;
-}
-
-int model_nalm_union(crs_model m) { return (m->Lc + 1) * (m->Lc + 1); }
-
-// coefficient table / diag choice for an operator
-enum OpKind { OP_A = 0, OP_PI = 1 };
-
-void run_band_ops(crs_model m, int nrhs, const double* in, const double* coef, bool pinv, hipStream_t s) {
-  for (size_t gi = 0; gi < m->groups.size(); ++gi) {
-    Group& g = m->groups[gi];
-    const int nmaps = (int)g.bands.size() * nrhs;
-    dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, nmaps);
-    hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, in, m->n, nrhs, m->ncomp, m->d_lk.p, m->d_coff.p,
-                       coef, m->nbands, g.bandids.p, g.lmax, m->ftab.p, m->Lmax, g.uhat.p, g.nalm);
-    CRS_HIP(hipGetLastError());
-    {
-      ProfScope ps(FAM_LEG_SYNTH, leg_flops(*g.plan, nmaps), s);
-      launch_leg_synth(leg_args(g.grid, *g.plan), nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
-    }
-    {
-      ProfScope ps(FAM_RING, ring_bytes(g.grid, g.lmax, nmaps, RING_ROUNDTRIP) +
-                                 (double)g.bands.size() * g.grid->npix * 8.0, s);
-      launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
-                  pinv ? g.wP.p : g.wA.p, nrhs, s);
-    }
-    {
-      ProfScope ps(FAM_LEG_ADJ, leg_flops(*g.plan, nmaps), s);
-      launch_leg_adjoint(leg_args(g.grid, *g.plan), nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
-                         (int64_t)nmaps * g.nalm, false, s);
-    }
-  }
-}
-
-void mix_back(crs_model m, int nrhs, double* out, const double* din, int dmode, const double* dtab,
-              const double* coef, hipStream_t s) {
-  dim3 gr((2 * (m->Lc + 1) + 255) / 256, m->Lc + 1, m->ncomp * nrhs);
-  hipLaunchKernelGGL(k_mix_back, gr, dim3(256), 0, s, out, din, m->n, nrhs, m->ncomp, m->d_lk.p, m->d_coff.p,
-                     coef, m->nbands, m->d_vptr.p, m->d_binfo.p, dmode, dtab, m->ftab.p, m->Lmax, m->Lc);
-  CRS_HIP(hipGetLastError());
-}
-
-void op_apply(crs_model m, OpKind kind, int nrhs, const double* in, double* out, hipStream_t s) {
-  ensure_ws(m, nrhs, s);
-  const bool pinv = kind == OP_PI;
-  const double* coef = pinv ? m->cP.p : m->cA.p;
-  run_band_ops(m, nrhs, in, coef, pinv, s);
-  if (pinv)
-    mix_back(m, nrhs, out, in, 2, m->dPi.p, coef, s);
-  else
-    mix_back(m, nrhs, out, in, 1, m->dInv.p, coef, s);
-}
-
-void diag_apply(crs_model m, int nrhs, const double* r, double* z, hipStream_t s) {
-  dim3 gr((2 * (m->Lc + 1) + 255) / 256, m->Lc + 1, nrhs);
-  hipLaunchKernelGGL(k_diag_apply, gr, dim3(256), 0, s, r, z, m->n, m->ncomp, m->d_lk.p, m->d_coff.p,
-                     m->Dinv.p, m->Lc);
-  CRS_HIP(hipGetLastError());
-}
-
-void precond_apply(crs_model m, int precond, int nrhs, const double* r, double* z, hipStream_t s) {
-  if (precond == CRS_PRECOND_PINV) {
-    op_apply(m, OP_PI, nrhs, r, z, s);
-  } else if (precond == CRS_PRECOND_DIAG) {
-    diag_apply(m, nrhs, r, z, s);
-  } else {
-    CRS_HIP(hipMemcpyAsync(z, r, (size_t)nrhs * m->n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  }
-}
-
 // M_diag setup: diag(Y^T tau Y) per band via the squared Legendre adjoint of
 // the ring spectrum of tau, then the N_comp x N_comp blocks on the host.
 void build_diag(crs_model m, hipStream_t s) {
@@ -612,18 +198,20 @@ void build_diag(crs_model m, hipStream_t s) {
   std::vector<std::vector<double>> dg(nb);
   for (int nu = 0; nu < nb; ++nu) {
     Band& b = m->bands[nu];
-    Group& g = m->groups[b.group];
-    ShtPlan& p = *g.plan;
+    ShtPlan& p = get_plan(b.grid, b.lmax, s);
+    const int ntiles = leg_adjoint_tiles(p.npairs, b.lmax);
+    const int64_t nalm = (int64_t)(b.lmax + 1) * (b.lmax + 1);
+    const int64_t pst = (int64_t)b.grid->nring * (b.lmax + 1);
     DevBuf<double2> ph;
     DevBuf<double> vp, out;
-    ph.alloc((size_t)g.pst);
-    vp.alloc((size_t)g.ntiles * g.nalm);
-    out.alloc((size_t)g.nalm);
-    launch_ring(g.grid, g.lmax, RING_DIAG, 1, ph.p, g.pst, b.tau.p, nullptr, g.grid->npix, nullptr, 1, s);
-    launch_leg_adjoint(leg_args(g.grid, p), 1, ph.p, g.pst, vp.p, g.nalm, g.nalm, true, s);
-    launch_hat_scale(p.f.p, g.lmax, 1, vp.p, g.nalm, g.ntiles, g.nalm, out.p, g.nalm, true, s);
-    dg[nu].resize(g.nalm);
-    CRS_HIP(hipMemcpyAsync(dg[nu].data(), out.p, g.nalm * sizeof(double), hipMemcpyDeviceToHost, s));
+    ph.alloc((size_t)pst);
+    vp.alloc((size_t)ntiles * nalm);
+    out.alloc((size_t)nalm);
+    launch_ring(b.grid, b.lmax, RING_DIAG, 1, ph.p, pst, b.tau.p, nullptr, b.grid->npix, nullptr, 1, s);
+    launch_leg_adjoint(leg_args(b.grid, p), 1, ph.p, pst, vp.p, nalm, nalm, true, s);
+    launch_hat_scale(p.f.p, b.lmax, 1, vp.p, nalm, ntiles, nalm, out.p, nalm, true, s);
+    dg[nu].resize(nalm);
+    CRS_HIP(hipMemcpyAsync(dg[nu].data(), out.p, nalm * sizeof(double), hipMemcpyDeviceToHost, s));
     CRS_HIP(hipStreamSynchronize(s));
   }
   const int64_t nu_ = (int64_t)(Lc + 1) * (Lc + 1);
@@ -684,7 +272,66 @@ void validate_desc(const crs_model_desc* d) {
   }
 }
 
+
+// The model's Exec for nrhs right-hand sides (kept per nrhs, built on first use).
+Exec& model_exec(crs_model m, int nrhs, hipStream_t s) {
+  auto it = m->execs.find(nrhs);
+  if (it != m->execs.end()) return *it->second;
+  auto e = make_exec({m}, nrhs, s);
+  Exec& ref = *e;
+  m->execs[nrhs] = std::move(e);
+  return ref;
+}
+
+void check_vec(crs_model m, int nrhs, const void* a, const void* b) {
+  CRS_CHECK(m != nullptr, CRS_EINVAL, "model is NULL");
+  CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
+  CRS_CHECK(a != nullptr && b != nullptr, CRS_EINVAL, "vector pointer is NULL");
+}
+
+// per (system, band) map pointers of a model's [nrhs][npix] band arrays
+std::vector<std::vector<const double*>> sys_band_ptrs(crs_model m, int nrhs, const double* const* arr) {
+  std::vector<std::vector<const double*>> out;
+  if (!arr) return out;
+  out.assign(nrhs, std::vector<const double*>(m->nbands, nullptr));
+  for (int r = 0; r < nrhs; ++r)
+    for (int nu = 0; nu < m->nbands; ++nu)
+      out[r][nu] = arr[nu] ? arr[nu] + (int64_t)r * m->bands[nu].npix : nullptr;
+  return out;
+}
+
 }  // namespace
+
+namespace crs {
+void launch_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, int nrhs, int64_t n, double* out,
+                           hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  int64_t nb = ((n + 3) / 4 + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_philox_normals, dim3((unsigned)nb, nrhs), dim3(256), 0, s, seed, stream, rhs0, n, out);
+  CRS_HIP(hipGetLastError());
+}
+
+// omega_1 (per band, streams 0x100 + nu) and omega_2 (stream 0x200) of the
+// constrained-realization right-hand side into the model's buffers.
+void model_draw_omegas(crs_model m, int nrhs, uint64_t seed, std::vector<const double*>& w1,
+                       const double*& w2, hipStream_t s) {
+  int64_t tot = 0;
+  for (auto& b : m->bands) tot += b.npix;
+  m->om1.alloc((size_t)tot * nrhs);
+  m->om2.alloc((size_t)m->n * nrhs);
+  w1.assign(m->nbands, nullptr);
+  int64_t o = 0;
+  for (int nu = 0; nu < m->nbands; ++nu) {
+    const int64_t np = m->bands[nu].npix;
+    launch_philox_normals(seed, (uint64_t)(0x100 + nu), 0, nrhs, np, m->om1.p + o, s);
+    w1[nu] = m->om1.p + o;
+    o += np * nrhs;
+  }
+  launch_philox_normals(seed, 0x200, 0, nrhs, m->n, m->om2.p, s);
+  w2 = m->om2.p;
+}
+}  // namespace crs
 
 using namespace crs;
 
@@ -740,43 +387,7 @@ int crs_model_create(const crs_model_desc* d, crs_stream st, crs_model* out) {
       for (int64_t i = 0; i < b.npix; ++i)
         tp[i] = b.tau_host[i] > 0.0 ? b.alpha2 * b.w_host[i] * b.w_host[i] / b.tau_host[i] : 0.0;
       b.tplus.upload(tp, s);
-      // group by (grid, lmax)
-      int gi = -1;
-      for (size_t k = 0; k < m->groups.size(); ++k)
-        if (m->groups[k].grid == b.grid && m->groups[k].lmax == b.lmax) gi = (int)k;
-      if (gi < 0) {
-        m->groups.emplace_back();
-        gi = (int)m->groups.size() - 1;
-        m->groups[gi].grid = b.grid;
-        m->groups[gi].lmax = b.lmax;
-      }
-      b.group = gi;
-      b.gidx = (int)m->groups[gi].bands.size();
-      m->groups[gi].bands.push_back(nu);
     }
-    for (auto& g : m->groups) {
-      g.plan = &get_plan(g.grid, g.lmax, s);
-      g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax);
-      g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
-      g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
-      std::vector<const double*> wa, wp;
-      for (int nu : g.bands) {
-        wa.push_back(m->bands[nu].tau.p);
-        wp.push_back(m->bands[nu].tplus.p);
-      }
-      g.wA.upload(wa, s);
-      g.wP.upload(wp, s);
-      g.bandids.upload(g.bands, s);
-    }
-    std::vector<int> binfo(4 * d->nbands);
-    for (int nu = 0; nu < d->nbands; ++nu) {
-      const Band& b = m->bands[nu];
-      binfo[4 * nu + 0] = b.lmax;
-      binfo[4 * nu + 1] = (int)m->groups[b.group].bands.size();
-      binfo[4 * nu + 2] = b.gidx;
-      binfo[4 * nu + 3] = m->groups[b.group].ntiles;
-    }
-    m->d_binfo.upload(binfo, s);
     m->d_lk.upload(m->lk, s);
     m->d_coff.upload(m->coff, s);
     build_ftab(m.get(), s);
@@ -786,12 +397,12 @@ int crs_model_create(const crs_model_desc* d, crs_stream st, crs_model* out) {
       build_diag(m.get(), s);
       m->has_diag = true;
     }
-    ensure_ws(m.get(), 1, s);
     CRS_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return CRS_OK;
   });
 }
+
 
 int crs_model_destroy(crs_model m) {
   return guarded([&] {
@@ -831,16 +442,10 @@ int crs_model_set_mixing(crs_model m, const double* q, crs_stream st) {
   });
 }
 
-static void check_vec(crs_model m, int nrhs, const void* a, const void* b) {
-  CRS_CHECK(m != nullptr, CRS_EINVAL, "model is NULL");
-  CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
-  CRS_CHECK(a != nullptr && b != nullptr, CRS_EINVAL, "vector pointer is NULL");
-}
-
 int apply_A(crs_model m, int nrhs, const double* x, double* y, crs_stream st) {
   return guarded([&] {
     check_vec(m, nrhs, x, y);
-    op_apply(m, OP_A, nrhs, x, y, (hipStream_t)st);
+    exec_apply(model_exec(m, nrhs, (hipStream_t)st), OP_A, x, y, (hipStream_t)st);
     return CRS_OK;
   });
 }
@@ -848,7 +453,7 @@ int apply_A(crs_model m, int nrhs, const double* x, double* y, crs_stream st) {
 int apply_pinv_precond(crs_model m, int nrhs, const double* r, double* z, crs_stream st) {
   return guarded([&] {
     check_vec(m, nrhs, r, z);
-    op_apply(m, OP_PI, nrhs, r, z, (hipStream_t)st);
+    exec_apply(model_exec(m, nrhs, (hipStream_t)st), OP_PI, r, z, (hipStream_t)st);
     return CRS_OK;
   });
 }
@@ -857,8 +462,7 @@ int apply_diag_precond(crs_model m, int nrhs, const double* r, double* z, crs_st
   return guarded([&] {
     check_vec(m, nrhs, r, z);
     CRS_CHECK(m->has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
-    ensure_ws(m, nrhs, (hipStream_t)st);
-    diag_apply(m, nrhs, r, z, (hipStream_t)st);
+    exec_diag(model_exec(m, nrhs, (hipStream_t)st), r, z, (hipStream_t)st);
     return CRS_OK;
   });
 }
@@ -867,145 +471,8 @@ int pcg_solve(crs_model m, int precond, int nrhs, const double* b, double* x, do
               int* iters, double* relres, double* history, crs_stream st) {
   return guarded([&] {
     check_vec(m, nrhs, b, x);
-    CRS_CHECK(precond == CRS_PRECOND_NONE || precond == CRS_PRECOND_DIAG || precond == CRS_PRECOND_PINV,
-              CRS_EINVAL, "unknown preconditioner");
-    CRS_CHECK(precond != CRS_PRECOND_DIAG || m->has_diag, CRS_EINVAL,
-              "model was created without CRS_MODEL_DIAG");
-    CRS_CHECK(rtol > 0.0 && maxiter >= 0, CRS_EINVAL, "rtol must be > 0 and maxiter >= 0");
     hipStream_t s = (hipStream_t)st;
-    ensure_ws(m, nrhs, s);
-    const int64_t n = m->n;
-    const dim3 vg = vgrid(n, nrhs);
-    const int nblk = (int)vg.x;
-    double* scal = m->scal.p;
-    auto dot_to = [&](const double* a, const double* bb, int op) {
-      hipLaunchKernelGGL(k_dot, vg, dim3(256), 0, s, a, bb, n, m->partial.p);
-      hipLaunchKernelGGL(k_scalar, dim3(nrhs), dim3(256), 0, s, op, m->partial.p, nblk, nrhs, scal);
-    };
-    std::vector<double> hs((size_t)nrhs * 8, 0.0), bb(nrhs);
-    for (int i = 0; i < nrhs; ++i) hs[i * 8 + S_ACTIVE] = 1.0;
-    CRS_HIP(hipMemcpyAsync(scal, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    // |b|^2
-    dot_to(b, b, 4);
-    CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CRS_HIP(hipStreamSynchronize(s));
-    std::vector<int> active(nrhs, 1), status(nrhs, 0), it_used(nrhs, 0);
-    for (int i = 0; i < nrhs; ++i) {
-      bb[i] = hs[i * 8 + S_TMP];
-      if (!(bb[i] > 0.0)) {
-        active[i] = 0;  // b = 0: x = 0 is the solution
-      }
-    }
-    // zero x for b = 0 rhs
-    for (int i = 0; i < nrhs; ++i)
-      if (!active[i]) CRS_HIP(hipMemsetAsync(x + (int64_t)i * n, 0, n * sizeof(double), s));
-    // r = b - A x
-    op_apply(m, OP_A, nrhs, x, m->q.p, s);
-    hipLaunchKernelGGL(k_sub, vg, dim3(256), 0, s, m->r.p, b, m->q.p, n, (const int*)nullptr);
-    precond_apply(m, precond, nrhs, m->r.p, m->z.p, s);
-    CRS_HIP(hipMemcpyAsync(m->p.p, m->z.p, (size_t)nrhs * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    for (int i = 0; i < nrhs; ++i) hs[i * 8 + S_ACTIVE] = active[i];
-    CRS_HIP(hipMemcpyAsync(scal, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    dot_to(m->r.p, m->z.p, 3);
-    CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CRS_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < nrhs; ++i) {
-      if (active[i] && hs[i * 8 + S_ACTIVE] == 0.0) {
-        active[i] = 0;
-        status[i] = hs[i * 8 + S_BREAK] != 0.0 ? 2 : 0;  // r = 0 (x0 exact) counts as converged
-      }
-    }
-    DevBuf<int>& dsel = m->dsel;
-    std::vector<int> sel(nrhs);
-    int it = 0;
-    auto any_active = [&] {
-      for (int i = 0; i < nrhs; ++i)
-        if (active[i]) return true;
-      return false;
-    };
-    while (any_active() && it < maxiter) {
-      ++it;
-      op_apply(m, OP_A, nrhs, m->p.p, m->q.p, s);
-      dot_to(m->p.p, m->q.p, 0);
-      hipLaunchKernelGGL(k_update_xr, vg, dim3(256), 0, s, x, m->r.p, m->p.p, m->q.p, n, scal, m->partial.p);
-      hipLaunchKernelGGL(k_scalar, dim3(nrhs), dim3(256), 0, s, 2, m->partial.p, nblk, nrhs, scal);
-      CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      CRS_HIP(hipStreamSynchronize(s));
-      bool cand = false;
-      for (int i = 0; i < nrhs; ++i) {
-        sel[i] = 0;
-        if (!active[i]) continue;
-        if (hs[i * 8 + S_BREAK] != 0.0) {
-          active[i] = 0;
-          status[i] = 2;
-          it_used[i] = it;
-          continue;
-        }
-        const double rel = std::sqrt(hs[i * 8 + S_RR] / bb[i]);
-        if (history) history[(size_t)(it - 1) * nrhs + i] = rel;
-        it_used[i] = it;
-        if (!std::isfinite(rel)) {
-          active[i] = 0;
-          status[i] = 2;
-          continue;
-        }
-        if (rel <= rtol) {
-          sel[i] = 1;
-          cand = true;
-        }
-      }
-      if (cand) {
-        // true residual of the candidates: t = b - A x
-        op_apply(m, OP_A, nrhs, x, m->q.p, s);
-        hipLaunchKernelGGL(k_sub, vg, dim3(256), 0, s, m->t.p, b, m->q.p, n, (const int*)nullptr);
-        dot_to(m->t.p, m->t.p, 4);
-        CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        CRS_HIP(hipStreamSynchronize(s));
-        bool restart = false;
-        for (int i = 0; i < nrhs; ++i) {
-          if (!sel[i]) continue;
-          if (std::sqrt(hs[i * 8 + S_TMP] / bb[i]) <= rtol) {
-            active[i] = 0;
-            status[i] = 0;
-            sel[i] = 0;
-          } else {
-            restart = true;  // keep sel[i] = 1: restart from the true residual
-          }
-        }
-        for (int i = 0; i < nrhs; ++i) {
-          hs[i * 8 + S_ACTIVE] = active[i];
-          hs[i * 8 + S_RESTART] = sel[i];
-        }
-        CRS_HIP(hipMemcpyAsync(scal, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        if (restart) {
-          CRS_HIP(hipMemcpyAsync(dsel.p, sel.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-          hipLaunchKernelGGL(k_copy_sel, vg, dim3(256), 0, s, m->r.p, m->t.p, n, dsel.p);
-        }
-        CRS_HIP(hipStreamSynchronize(s));
-      }
-      if (!any_active()) break;
-      precond_apply(m, precond, nrhs, m->r.p, m->z.p, s);
-      dot_to(m->r.p, m->z.p, 1);
-      hipLaunchKernelGGL(k_update_p, vg, dim3(256), 0, s, m->p.p, m->z.p, n, scal);
-    }
-    for (int i = 0; i < nrhs; ++i)
-      if (active[i]) status[i] = 1;  // maxiter
-    // final true residuals
-    op_apply(m, OP_A, nrhs, x, m->q.p, s);
-    hipLaunchKernelGGL(k_sub, vg, dim3(256), 0, s, m->t.p, b, m->q.p, n, (const int*)nullptr);
-    dot_to(m->t.p, m->t.p, 4);
-    CRS_HIP(hipMemcpyAsync(hs.data(), scal, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CRS_HIP(hipStreamSynchronize(s));
-    int ret = CRS_OK;
-    for (int i = 0; i < nrhs; ++i) {
-      if (iters) iters[i] = it_used[i];
-      if (relres) relres[i] = bb[i] > 0 ? std::sqrt(hs[i * 8 + S_TMP] / bb[i]) : 0.0;
-      if (status[i] == 2) ret = CRS_EBREAKDOWN;
-      else if (status[i] == 1 && ret == CRS_OK) ret = CRS_ENOTCONV;
-    }
-    if (ret == CRS_EBREAKDOWN) set_error(ret, "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)");
-    if (ret == CRS_ENOTCONV) set_error(ret, "PCG reached maxiter");
-    return ret;
+    return exec_pcg(model_exec(m, nrhs, s), precond, b, x, rtol, maxiter, iters, relres, history, false, s);
   });
 }
 
@@ -1015,25 +482,7 @@ int build_rhs(crs_model m, int nrhs, const double* const* d, const double* const
     CRS_CHECK(m != nullptr && b != nullptr, CRS_EINVAL, "model or b is NULL");
     CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
     hipStream_t s = (hipStream_t)st;
-    ensure_ws(m, nrhs, s);
-    for (auto& g : m->groups) {
-      const int nmaps = (int)g.bands.size() * nrhs;
-      const int64_t npix = g.grid->npix;
-      g.pix.alloc((size_t)nmaps * npix);
-      for (size_t gi = 0; gi < g.bands.size(); ++gi) {
-        const int nu = g.bands[gi];
-        const double* dv = d ? d[nu] : nullptr;
-        const double* wv = omega1 ? omega1[nu] : nullptr;
-        hipLaunchKernelGGL(k_pix_rhs, vgrid(npix, nrhs), dim3(256), 0, s, g.pix.p + (int64_t)gi * nrhs * npix,
-                           m->bands[nu].tau.p, dv, wv, npix);
-      }
-      CRS_HIP(hipGetLastError());
-      launch_ring(g.grid, g.lmax, RING_ADJOINT, nmaps, g.phase.p, g.pst, g.pix.p, nullptr, npix,
-                  nullptr, 1, s);
-      launch_leg_adjoint(leg_args(g.grid, *g.plan), nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
-                         (int64_t)nmaps * g.nalm, false, s);
-    }
-    mix_back(m, nrhs, b, omega2, omega2 ? 1 : 0, m->dSqrt.p, m->cA.p, s);
+    exec_rhs(model_exec(m, nrhs, s), sys_band_ptrs(m, nrhs, d), sys_band_ptrs(m, nrhs, omega1), omega2, b, s);
     return CRS_OK;
   });
 }
@@ -1044,22 +493,10 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
     CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
     for (int nu = 0; nu < m->nbands; ++nu) CRS_CHECK(maps[nu] != nullptr, CRS_EINVAL, "maps entry is NULL");
     hipStream_t s = (hipStream_t)st;
-    ensure_ws(m, nrhs, s);
-    for (auto& g : m->groups) {
-      const int nmaps = (int)g.bands.size() * nrhs;
-      const int64_t npix = g.grid->npix;
-      g.pix.alloc((size_t)nmaps * npix);
-      dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, nmaps);
-      hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, x, m->n, nrhs, m->ncomp, m->d_lk.p, m->d_coff.p,
-                         m->cA.p, m->nbands, g.bandids.p, g.lmax, m->ftab.p, m->Lmax, g.uhat.p, g.nalm);
-      CRS_HIP(hipGetLastError());
-      launch_leg_synth(leg_args(g.grid, *g.plan), nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
-      launch_ring(g.grid, g.lmax, RING_SYNTH, nmaps, g.phase.p, g.pst, nullptr, g.pix.p, npix,
-                  nullptr, 1, s);
-      for (size_t gi = 0; gi < g.bands.size(); ++gi)
-        CRS_HIP(hipMemcpyAsync(maps[g.bands[gi]], g.pix.p + (int64_t)gi * nrhs * npix,
-                               (size_t)nrhs * npix * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
+    std::vector<std::vector<double*>> mp(nrhs, std::vector<double*>(m->nbands));
+    for (int r = 0; r < nrhs; ++r)
+      for (int nu = 0; nu < m->nbands; ++nu) mp[r][nu] = maps[nu] + (int64_t)r * m->bands[nu].npix;
+    exec_project(model_exec(m, nrhs, s), x, mp, s);
     return CRS_OK;
   });
 }
@@ -1067,11 +504,7 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
 int crs_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs, int64_t n, double* out, crs_stream st) {
   return guarded([&] {
     CRS_CHECK(out != nullptr && n >= 0, CRS_EINVAL, "out is NULL or n < 0");
-    if (n == 0) return CRS_OK;
-    int64_t nb = ((n + 3) / 4 + 255) / 256;
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_philox_normals, dim3((unsigned)nb, 1), dim3(256), 0, (hipStream_t)st, seed, stream, rhs, n, out);
-    CRS_HIP(hipGetLastError());
+    launch_philox_normals(seed, stream, rhs, 1, n, out, (hipStream_t)st);
     return CRS_OK;
   });
 }
@@ -1084,37 +517,16 @@ int constrained_realization(crs_model m, int nrhs, const double* const* d, uint6
     CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
     CRS_CHECK(mode == CRS_MODE_WF || mode == CRS_MODE_CR, CRS_EINVAL, "mode must be WF or CR");
     hipStream_t s = (hipStream_t)st;
-    ensure_ws(m, nrhs, s);
-    std::vector<const double*> w1(m->nbands, nullptr);
+    Exec& e = model_exec(m, nrhs, s);
+    std::vector<const double*> w1;
     const double* w2 = nullptr;
-    if (mode == CRS_MODE_CR) {
-      int64_t tot = 0;
-      for (auto& b : m->bands) tot += b.npix;
-      m->om1.alloc((size_t)tot * nrhs);
-      m->om2.alloc((size_t)m->n * nrhs);
-      int64_t o = 0;
-      for (int nu = 0; nu < m->nbands; ++nu) {
-        const int64_t np = m->bands[nu].npix;
-        int64_t nb = ((np + 3) / 4 + 255) / 256;
-        if (nb > 4096) nb = 4096;
-        hipLaunchKernelGGL(k_philox_normals, dim3((unsigned)nb, nrhs), dim3(256), 0, s, seed,
-                           (uint64_t)(0x100 + nu), (uint64_t)0, np, m->om1.p + o);
-        w1[nu] = m->om1.p + o;
-        o += np * nrhs;
-      }
-      int64_t nb = ((m->n + 3) / 4 + 255) / 256;
-      if (nb > 4096) nb = 4096;
-      hipLaunchKernelGGL(k_philox_normals, dim3((unsigned)nb, nrhs), dim3(256), 0, s, seed, (uint64_t)0x200,
-                         (uint64_t)0, m->n, m->om2.p);
-      CRS_HIP(hipGetLastError());
-      w2 = m->om2.p;
-    }
+    if (mode == CRS_MODE_CR) model_draw_omegas(m, nrhs, seed, w1, w2, s);
     // the right-hand side is kept in a model-owned buffer
     m->bcr.alloc((size_t)m->n * nrhs);
-    int rc = build_rhs(m, nrhs, d, mode == CRS_MODE_CR ? w1.data() : nullptr, w2, m->bcr.p, st);
-    if (rc != CRS_OK) return rc;
+    exec_rhs(e, sys_band_ptrs(m, nrhs, d), sys_band_ptrs(m, nrhs, mode == CRS_MODE_CR ? w1.data() : nullptr), w2,
+             m->bcr.p, s);
     CRS_HIP(hipMemsetAsync(x, 0, (size_t)m->n * nrhs * sizeof(double), s));
-    rc = pcg_solve(m, precond, nrhs, m->bcr.p, x, rtol, maxiter, iters, relres, nullptr, st);
+    const int rc = exec_pcg(e, precond, m->bcr.p, x, rtol, maxiter, iters, relres, nullptr, false, s);
     CRS_HIP(hipStreamSynchronize(s));
     return rc;
   });

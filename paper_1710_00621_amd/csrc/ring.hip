@@ -283,6 +283,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   double2* G = a.any_blue ? wc2 + kBlueMax / 64 : wf2;  // fold scratch (rings with N <= NT)
   const int r = a.rings[blockIdx.x];
   const int map = blockIdx.y;
+  if (a.skip.off(map)) return;  // whole block: before any barrier
   const int tid = threadIdx.x;
   const int L = a.lmax;
   const int N = a.nphi[r];
@@ -425,9 +426,10 @@ RingArgs ring_args(crs_grid g, int lmax);
 
 void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase, int64_t pstride,
                  const double* map_in, double* map_out, int64_t mstride,
-                 const double* const* weights, int maps_per_weight, hipStream_t s) {
+                 const double* const* weights, int maps_per_weight, hipStream_t s, MapSkip skip) {
   CRS_CHECK(lmax < 65536, CRS_EUNSUPPORTED, "lmax above 65535 is not supported by the ring stage");
-  const RingArgs base = ring_args(g, lmax);
+  RingArgs base = ring_args(g, lmax);
+  base.skip = skip;
   const int mpw = maps_per_weight < 1 ? 1 : maps_per_weight;
   const int md = (int)mode;
   for (size_t c = 0; c < g->ring_classes.size(); ++c) {
