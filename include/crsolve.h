@@ -187,6 +187,25 @@ int constrained_realization(crs_model m, int nrhs, const double* const* d, uint6
  * (Used to synthesise data d = P s + n.) */
 int crs_model_project(crs_model m, int nrhs, const double* x, double* const* maps, crs_stream s);
 
+/* ------------------------------------------------------ differentiation
+ * Building blocks of implicit gradients through the solve (Sect. 2.3 with
+ * the mixing q_{nu,k} of Sect. 3.3 as parameters).  All vectors are device
+ * nrhs x n; dq is device nrhs x nbands x ncomp (row-major), overwritten.
+ *
+ * apply_prior_inv: y = S^-1 x (C_{k,l}^-1 per coefficient).
+ * apply_dA_dmix:   dq[r][nu][k] = -lam_r^T (dA/dq_{nu,k}) x_r
+ *                  = -(lam_{r,k} . B_nu Y^T tau Y B_nu u^x_nu + x_{r,k} . B_nu Y^T tau Y B_nu u^lam_nu),
+ *                  u^v_nu = sum_k' q_{nu,k'} v_k'  (two SHT round trips per band).
+ * apply_db_dmix:   dq[r][nu][k] = lam_r^T (db/dq_{nu,k}) for b = sum_nu P_nu^T tau d_nu
+ *                  = lam_{r,k} . B_nu Y^T (tau d_{r,nu}); d as in build_rhs (host array of
+ *                  nbands device pointers, each nrhs x npix_nu; NULL entries are zero).
+ */
+int apply_prior_inv(crs_model m, int nrhs, const double* x, double* y, crs_stream s);
+int apply_dA_dmix(crs_model m, int nrhs, const double* lam, const double* x, double* dq,
+                  crs_stream s);
+int apply_db_dmix(crs_model m, int nrhs, const double* lam, const double* const* d, double* dq,
+                  crs_stream s);
+
 /* Device normals of the library's Philox stream (the omega draws of
  * constrained_realization): out[i] for i < n, device array. */
 int crs_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs, int64_t n, double* out,

@@ -77,6 +77,9 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_int, vp, c_int_p,
                                                c_double_p, vp]),
     "crs_model_project": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), vp]),
+    "apply_prior_inv": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+    "apply_dA_dmix": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
+    "apply_db_dmix": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), vp, vp]),
     "crs_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]),
     "crs_batch_destroy": (ctypes.c_int, [vp]),
     "crs_batch_info": (ctypes.c_int, [vp, c_int_p, c_int64_p]),

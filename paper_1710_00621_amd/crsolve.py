@@ -138,6 +138,7 @@ class Model:
 
     def __init__(self, bands, comps, q, diag=True):
         self.grids = [b["grid"] for b in bands]
+        self.taus = [np.asarray(b["tau"], dtype=np.float64) for b in bands]
         self.ncomp = len(comps)
         self.nbands = len(bands)
         self.lmax_comp = [int(c["lmax"]) for c in comps]

@@ -153,6 +153,73 @@ __device__ __forceinline__ double block_sum256(double acc, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// y[sys][coff_k + idx] = C^-1_{k,l} x[sys][coff_k + idx]
+__global__ void k_prior(double* __restrict__ y, const double* __restrict__ x, const SysDev* __restrict__ sys,
+                        const ProbDev* __restrict__ probs, const int2* __restrict__ rows) {
+  const int m = blockIdx.y;
+  const int2 row = rows[blockIdx.z];
+  const SysDev S = sys[row.x];
+  const ProbDev P = probs[S.prob];
+  const int k = row.y;
+  const int Lk = P.lk[k];
+  if (m > Lk) return;
+  const int nsl = Lk - m + 1;
+  const int np = (m == 0) ? 1 : 2;
+  const int64_t o = S.off + P.coff[k] + moff_h(Lk, m);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x)
+    y[o + i] = P.dInv[(int64_t)(m + i % nsl) * P.nc + k] * x[o + i];
+}
+
+// One block per (r, nu, k) of a single-problem Exec (see exec_mix_grad).
+__global__ __launch_bounds__(256) void k_dq(const double* __restrict__ va, int sa0, const double* __restrict__ vb,
+                                            int sb0, double sign, const SysDev* __restrict__ sys,
+                                            const ProbDev* __restrict__ probs, const double* __restrict__ beamtab,
+                                            double* __restrict__ dq) {
+  __shared__ double red[4];
+  const ProbDev P = probs[0];
+  const int nb = P.nb, nc = P.nc;
+  const int k = blockIdx.x % nc;
+  const int nu = (blockIdx.x / nc) % nb;
+  const int r = blockIdx.x / (nc * nb);
+  const int Lk = P.lk[k];
+  const int* bi = P.binfo + 5 * nu;
+  const int Lb = bi[0];
+  const int Lm = min(Lk, Lb);
+  const int64_t nalm = (int64_t)(Lb + 1) * (Lb + 1);
+  const int64_t tstride = (int64_t)bi[1] * nalm;
+  const SysDev SA = sys[sa0 + r];
+  const double* VA = P.vptr[nu] + (int64_t)(bi[2] + SA.rhs * bi[4]) * nalm;
+  const double* VB = nullptr;
+  const double* xb = nullptr;
+  if (vb) {
+    const SysDev SB = sys[sb0 + r];
+    VB = P.vptr[nu] + (int64_t)(bi[2] + SB.rhs * bi[4]) * nalm;
+    xb = vb + SA.off;
+  }
+  const double* xa = va + SA.off;
+  double acc = 0.0;
+  for (int m = 0; m <= Lm; ++m) {
+    const int np = (m == 0) ? 1 : 2;
+    const int ns = Lm - m + 1;
+    const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
+    for (int i = threadIdx.x; i < np * ns; i += 256) {
+      const int part = i / ns, ll = i % ns, l = m + ll;
+      const int64_t ik = P.coff[k] + moff_h(Lk, m) + (int64_t)part * (Lk - m + 1) + ll;
+      const int64_t ib = moff_h(Lb, m) + (int64_t)part * (Lb - m + 1) + ll;
+      const double fs = beamtab[(int64_t)l * nb + nu] * cm * P.ftab[tri_h(P.Lf, m) + ll];
+      double sa = 0.0, sb = 0.0;
+      for (int t = 0; t < bi[3]; ++t) {
+        sa += VA[t * tstride + ib];
+        if (VB) sb += VB[t * tstride + ib];
+      }
+      acc = fma(xa[ik], fs * sa, acc);
+      if (VB) acc = fma(xb[ik], fs * sb, acc);
+    }
+  }
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) dq[blockIdx.x] = sign * t;
+}
+
 // partial[sys][blk] = this block's slice of a . b (grid: kDotBlocks x nsys)
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
                                              const SysDev* __restrict__ sys, double* __restrict__ partial) {
@@ -432,7 +499,7 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   return e;
 }
 
-void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done) {
+void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip_done) {
   const bool pinv = kind == OP_PI;
   const double* act = skip_done ? e.scal.p + S_ACTIVE : nullptr;
   for (auto& g : e.groups) {
@@ -462,7 +529,12 @@ void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t
       launch_leg_adjoint(la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false, s);
     }
   }
-  if (pinv)
+}
+
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done) {
+  exec_bands(e, kind, in, s, skip_done);
+  const double* act = skip_done ? e.scal.p + S_ACTIVE : nullptr;
+  if (kind == OP_PI)
     mix_back(e, out, in, 2, 0, 1, s, act);
   else
     mix_back(e, out, in, 1, 0, 0, s, act);
@@ -475,9 +547,8 @@ void exec_diag(Exec& e, const double* r, double* z, hipStream_t s) {
   CRS_HIP(hipGetLastError());
 }
 
-void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
-              const std::vector<std::vector<const double*>>& w1, const double* w2, double* b,
-              hipStream_t s) {
+void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,
+                    const std::vector<std::vector<const double*>>& w1, hipStream_t s) {
   for (auto& g : e.groups) {
     const int64_t npix = g.grid->npix;
     std::vector<const double*> dp(g.nmaps), wp(g.nmaps);
@@ -496,9 +567,32 @@ void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
     launch_leg_adjoint(leg_args(g.grid, *g.plan), g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
                        (int64_t)g.nmaps * g.nalm, false, s);
   }
-  mix_back(e, b, w2, w2 ? 1 : 0, 1, 0, s);
   // the pointer tables were uploaded from host temporaries: finish before they go
   CRS_HIP(hipStreamSynchronize(s));
+}
+
+void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
+              const std::vector<std::vector<const double*>>& w1, const double* w2, double* b,
+              hipStream_t s) {
+  exec_rhs_bands(e, d, w1, s);
+  mix_back(e, b, w2, w2 ? 1 : 0, 1, 0, s);
+}
+
+void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s) {
+  // the back-mix with no band terms: y = C^-1 x
+  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nrows);
+  hipLaunchKernelGGL(k_prior, gr, dim3(256), 0, s, y, x, e.dsys.p, e.dprobs.p, e.rows.p);
+  CRS_HIP(hipGetLastError());
+}
+
+// dq[r][nu][k] = sign sum_lm ( va_r,k(lm) V(sa0 + r, nu)(lm) + vb_r,k(lm) V(sb0 + r, nu)(lm) ),
+// V(s, nu) = b_{nu,l} c_m f_lm sum_t vpart_nu[t][map(s, nu)]: the band-nu adjoint of system s.
+void exec_mix_grad(Exec& e, const double* va, int sa0, const double* vb, int sb0, int nrhs, double sign,
+                   const double* beamtab, double* dq, hipStream_t s) {
+  const crs_model m = e.probs[0];
+  dim3 gr(nrhs * m->nbands * m->ncomp);
+  hipLaunchKernelGGL(k_dq, gr, dim3(256), 0, s, va, sa0, vb, sb0, sign, e.dsys.p, e.dprobs.p, beamtab, dq);
+  CRS_HIP(hipGetLastError());
 }
 
 void exec_project(Exec& e, const double* x, const std::vector<std::vector<double*>>& maps, hipStream_t s) {

@@ -106,6 +106,14 @@ enum OpKind { OP_A = 0, OP_PI = 1 };
 // not written); used inside the iteration.
 void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done = false);
 void exec_diag(Exec& e, const double* r, double* z, hipStream_t s);
+// the band half of exec_apply: every group's adjoint partial sums, no back-mix
+void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip_done = false);
+void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
+// the band half of exec_rhs (data / omega_1 terms only)
+void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,
+                    const std::vector<std::vector<const double*>>& w1, hipStream_t s);
+void exec_mix_grad(Exec& e, const double* va, int sa0, const double* vb, int sb0, int nrhs, double sign,
+                   const double* beamtab, double* dq, hipStream_t s);
 // b = sum P^T (tau d + tau^1/2 w1) + C^-1/2 w2; d, w1: per (system, band) host
 // tables of device map pointers indexed [sys][band] (NULL = zero); w2 stacked.
 void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
@@ -139,6 +147,8 @@ struct crs_model_s {
   crs::DevBuf<double> dInv, dSqrt;   // [Lmax+1][nc] diagonal prior terms
   crs::DevBuf<double> dPi;           // [Lmax+1][nc][nc]
   crs::DevBuf<double> ftab;          // f_lm triangle at Lmax
+  crs::DevBuf<double> beamtab;       // [Lmax+1][nb] b_{nu,l} (0 above L_nu)
+  crs::DevBuf<double> gwork;         // [x; lambda] stacked for the mixing gradient
   crs::DevBuf<double> Dinv;          // [(Lc+1)^2][nc][nc]
   crs::DevBuf<int> d_lk;
   crs::DevBuf<int64_t> d_coff;

@@ -176,10 +176,13 @@ void build_pinv_tables(crs_model m, hipStream_t s) {
 void build_mix_tables(crs_model m, hipStream_t s) {
   const int nb = m->nbands, nc = m->ncomp, L = m->Lmax;
   std::vector<double> cA((size_t)(L + 1) * nb * nc, 0.0), di((size_t)(L + 1) * nc, 0.0), ds(di.size(), 0.0);
+  std::vector<double> bt((size_t)(L + 1) * nb, 0.0);
   for (int l = 0; l <= L; ++l) {
     for (int nu = 0; nu < nb; ++nu)
-      if (l <= m->bands[nu].lmax)
+      if (l <= m->bands[nu].lmax) {
+        bt[(size_t)l * nb + nu] = m->bands[nu].beam[l];
         for (int k = 0; k < nc; ++k) cA[((size_t)l * nb + nu) * nc + k] = m->bands[nu].beam[l] * m->bands[nu].q[k];
+      }
     for (int k = 0; k < nc; ++k)
       if (l <= m->lk[k]) {
         di[(size_t)l * nc + k] = m->invcl[k][l];
@@ -187,6 +190,7 @@ void build_mix_tables(crs_model m, hipStream_t s) {
       }
   }
   m->cA.upload(cA, s);
+  m->beamtab.upload(bt, s);
   m->dInv.upload(di, s);
   m->dSqrt.upload(ds, s);
 }
@@ -497,6 +501,44 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
     for (int r = 0; r < nrhs; ++r)
       for (int nu = 0; nu < m->nbands; ++nu) mp[r][nu] = maps[nu] + (int64_t)r * m->bands[nu].npix;
     exec_project(model_exec(m, nrhs, s), x, mp, s);
+    return CRS_OK;
+  });
+}
+
+int apply_prior_inv(crs_model m, int nrhs, const double* x, double* y, crs_stream st) {
+  return guarded([&] {
+    check_vec(m, nrhs, x, y);
+    exec_prior_inv(model_exec(m, nrhs, (hipStream_t)st), x, y, (hipStream_t)st);
+    return CRS_OK;
+  });
+}
+
+int apply_dA_dmix(crs_model m, int nrhs, const double* lam, const double* x, double* dq, crs_stream st) {
+  return guarded([&] {
+    check_vec(m, nrhs, lam, x);
+    CRS_CHECK(dq != nullptr, CRS_EINVAL, "dq is NULL");
+    hipStream_t s = (hipStream_t)st;
+    // systems [x_0 .. x_{nrhs-1}, lam_0 .. lam_{nrhs-1}] through the band round trips
+    Exec& e = model_exec(m, 2 * nrhs, s);
+    const size_t nn = (size_t)nrhs * m->n;
+    m->gwork.alloc(2 * nn);
+    CRS_HIP(hipMemcpyAsync(m->gwork.p, x, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CRS_HIP(hipMemcpyAsync(m->gwork.p + nn, lam, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    exec_bands(e, OP_A, m->gwork.p, s);
+    // -(lam_k . V(x) + x_k . V(lam)); lam_r sits at system nrhs + r of gwork
+    exec_mix_grad(e, m->gwork.p + nn, 0, m->gwork.p, nrhs, nrhs, -1.0, m->beamtab.p, dq, s);
+    return CRS_OK;
+  });
+}
+
+int apply_db_dmix(crs_model m, int nrhs, const double* lam, const double* const* d, double* dq, crs_stream st) {
+  return guarded([&] {
+    check_vec(m, nrhs, lam, dq);
+    CRS_CHECK(d != nullptr, CRS_EINVAL, "d is NULL");
+    hipStream_t s = (hipStream_t)st;
+    Exec& e = model_exec(m, nrhs, s);
+    exec_rhs_bands(e, sys_band_ptrs(m, nrhs, d), {}, s);
+    exec_mix_grad(e, lam, 0, nullptr, 0, nrhs, 1.0, m->beamtab.p, dq, s);
     return CRS_OK;
   });
 }
