@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sht-roofline", action="store_true")
     ap.add_argument("--no-multires", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a dispatch of known "
+                         "traffic for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: every GPU box here has one MI355X and the solver does "
@@ -244,6 +247,13 @@ def main():
     from paper_1710_00621_amd import crsolve, inputs
 
     dev = torch.device("cuda:0")
+    if a.copy_probe_mb > 0:
+        nel = a.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev)
     torch.cuda.synchronize()
