@@ -22,6 +22,9 @@ OUT = os.path.join(PKG, "libcrsolve.so")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA operands and accumulators in ordinary VGPRs (no AGPR copies around
+    # every matrix instruction inside loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
 ]
 

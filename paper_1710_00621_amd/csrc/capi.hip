@@ -303,7 +303,7 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     GridWork& w = *g->work;
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
     const int64_t pst = (int64_t)g->nring * (lmax + 1);
-    const int ntiles = leg_adjoint_tiles(p.npairs, lmax);
+    const int ntiles = leg_adjoint_tiles(p.npairs, lmax, nmaps);
     w.phase.alloc((size_t)nmaps * pst);
     w.vpart.alloc((size_t)ntiles * nmaps * nalm);
     {

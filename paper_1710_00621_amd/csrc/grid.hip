@@ -395,7 +395,8 @@ ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s) {
   plan->lmax = L;
   plan->npairs = (g->nring + 1) / 2;
   int64_t ntri = (int64_t)(L + 1) * (L + 2) / 2;
-  std::vector<double> gt(ntri, 0.0), ft(ntri, 0.0);
+  // g carries 8 trailing zeros: the MFMA synthesis reads it in aligned groups of 8 past L
+  std::vector<double> gt(ntri + 8, 0.0), ft(ntri, 0.0);
   for (int m = 0; m <= L; ++m) {
     int64_t o = tri_off(L, m) - m;
     ft[o + m] = 1.0;

@@ -185,7 +185,7 @@ struct LegArgs {
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s);
 // Adjoint: writes ntiles partial vectors vpart[tile][map][nalm]; returns ntiles.
-int leg_adjoint_tiles(int npairs, int lmax);
+int leg_adjoint_tiles(int npairs, int lmax, int nmaps);
 void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s);

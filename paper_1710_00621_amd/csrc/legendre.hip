@@ -329,6 +329,140 @@ __global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const d
     synth_wave<NM, R, true>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
 }
 
+// ------------------------------------------------------ synthesis, MFMA
+// For many maps the l-contraction F_par[p][col] = sum_{l of parity par}
+// lambda_lm(p) u[l][col] is a dense product: rows = ring pairs, K = values of
+// l of one parity (l - m even: E, odd: O), N = 16 columns = 8 maps x (cos,
+// sin).  Operand layouts of v_mfma_f64_16x16x4 on gfx950 (measured): A lane t
+// = A[t % 16][t / 16], B lane t = B[t / 16][t % 16], D lane t register r =
+// D[t / 16 + 4 r][t % 16].
+// One wave owns (m, 64 ring pairs, 8 maps); lane t runs the recurrence of
+// pair t.  Each block of 8 steps [lb, lb + 8) (lb - m even) goes through a
+// wave-private LDS tile lam[8][64] so that row block rb (pairs 16 rb ..
+// 16 rb + 15) can be handed to the MFMA as A (lane (i, k) takes lam[2k][16 rb
+// + i] for E, lam[2k + 1][...] for O); B is u at l = lb + 2k (+1) for the 16
+// columns.  8 MFMAs per block, start indices injected at wave-uniform event
+// blocks as in the vector kernels.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS traffic done
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(256) void k_leg_synth_mfma(LegArgs a, int nmaps, const double* __restrict__ uhat,
+                                                        int64_t ustride, double2* __restrict__ phase,
+                                                        int64_t pstride, int ntiles) {
+  __shared__ double lamsh[4][8 * 64];
+  int mb, tile;
+  block_coords(ntiles, mb, tile);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = mb * 4 + wave;
+  const int L = a.lmax;
+  if (m > L) return;
+  const int mg = blockIdx.y;
+  if (a.skip.act) {
+    bool any = false;
+    for (int k = 0; k < 8 && mg * 8 + k < nmaps; ++k) any = any || !a.skip.off(mg * 8 + k);
+    if (!any) return;
+  }
+  double* lam = lamsh[wave];
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int p = tile * 64 + lane;
+  const bool valid = p < a.npairs;
+  const double z = valid ? a.zpair[p] : 0.0;
+  const int ls = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
+  const double2 st = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
+  // B column of this lane: map mg * 8 + j / 2, part j & 1 (cos, sin)
+  const int j = i16;
+  const int map = mg * 8 + (j >> 1), cs = j & 1;
+  const double* __restrict__ ub =
+      (map < nmaps && !(m == 0 && cs == 1)) ? uhat + (int64_t)map * ustride + moff(L, m) + cs * (L - m + 1) - m
+                                           : nullptr;
+  cdouble* gb = as_const(a.g + tri(L, m) - m);  // 8 zeros follow the table
+  // B loads are unconditional (clamped index, then masked) so that the
+  // in-order vector-memory counter lets the next block's loads stay in flight
+  const double* __restrict__ ubase = ub ? ub : uhat + m;
+  const double bmask = ub ? 1.0 : 0.0;
+  auto loadB = [&](int l) {
+    const double v = ubase[l <= L ? l : L];
+    return v * (l <= L ? bmask : 0.0);  // the value is always used: the load stays unconditional
+  };
+  const int lfirst = wave_min(ls);
+  v4d DE[4], DO[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    DE[rb] = v4d{0.0, 0.0, 0.0, 0.0};
+    DO[rb] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  if (lfirst <= L) {
+    int lb = lfirst - ((lfirst - m) & 1);
+    int nx = lfirst;  // next l at which some lane starts
+    double a0 = 0.0, a1 = 0.0;
+    double bE = loadB(lb + 2 * kq);
+    double bO = loadB(lb + 2 * kq + 1);
+    for (; lb <= L; lb += 8) {
+      lb = __builtin_amdgcn_readfirstlane(lb);
+      const double nE = loadB(lb + 8 + 2 * kq);
+      const double nO = loadB(lb + 9 + 2 * kq);
+      double gv[8];
+      cdouble* gp = gb + lb;
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) gv[s2] = gp[s2];
+      if (nx >= lb + 8) {
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+          const double cc = fma(gv[s2] * z, a1, -a0);
+          a0 = a1;
+          a1 = cc;
+          lam[s2 * 64 + lane] = cc;
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+          double cc = fma(gv[s2] * z, a1, -a0);
+          double pv = a1;
+          if (ls == lb + s2) {
+            cc = st.y;
+            pv = st.x;
+          }
+          a0 = pv;
+          a1 = cc;
+          lam[s2 * 64 + lane] = cc;
+        }
+        nx = wave_min(ls >= lb + 8 ? ls : INT_MAX);
+      }
+      lds_wave_sync();
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const double aE = lam[(2 * kq) * 64 + 16 * rb + i16];
+        const double aO = lam[(2 * kq + 1) * 64 + 16 * rb + i16];
+        DE[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, bE, DE[rb], 0, 0, 0);
+        DO[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, bO, DO[rb], 0, 0, 0);
+      }
+      // the next block's LDS writes follow these reads in this wave's program
+      // order, which the LDS preserves; only keep the compiler from hoisting them
+      __builtin_amdgcn_wave_barrier();
+      bE = nE;
+      bO = nO;
+    }
+  }
+  // D[rb][row = kq + 4 r][col = j]: ring pair tile*64 + 16 rb + kq + 4 r
+  if (map >= nmaps) return;
+  double* ph = reinterpret_cast<double*>(phase + (int64_t)map * pstride);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pp = tile * 64 + 16 * rb + kq + 4 * r;
+      if (pp >= a.npairs) continue;
+      const int rs = a.nring - 1 - pp;
+      ph[2 * ((int64_t)pp * (L + 1) + m) + cs] = DE[rb][r] + DO[rb][r];
+      if (rs != pp) ph[2 * ((int64_t)rs * (L + 1) + m) + cs] = DE[rb][r] - DO[rb][r];
+    }
+}
+
 // --------------------------------------------------------------- adjoint
 // Same wave decomposition.  Per l every lane sums its groups' products into
 // P[s]; each chunk of CH steps is reduced over the wave's 64 lanes through a
@@ -496,6 +630,135 @@ __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const
     adjoint_wave<NM, R, SQ, true>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
 }
 
+// -------------------------------------------------------- adjoint, MFMA
+// v_par[l][col] = sum_p lambda_lm(p) H_par(p)[col] as a dense product: rows =
+// 16 values of l of one parity, K = ring pairs, N = 16 columns (8 maps x cos,
+// sin).  One wave owns (m, 64 ring pairs, 8 maps); lane t runs the recurrence
+// of pair t and writes each chunk of 32 steps [lb, lb + 32) (lb - m even) to a
+// wave-private LDS tile lam[32][64]; K-block kb (pairs 4 kb .. 4 kb + 3) then
+// feeds the MFMA with A lane (i, k) = lam[2 i (+1)][4 kb + k] and B lane
+// (j, k) = H_par(4 kb + k)[j] (held in registers: 16 K-blocks x E/O).  The
+// 16 x 16 results of a chunk are the wave's partial v for 32 values of l.
+__global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, const double2* __restrict__ phase,
+                                                          int64_t pstride, double* __restrict__ vpart,
+                                                          int64_t vstride, int64_t tstride, int ntiles) {
+  // rows padded to 65 doubles: the transposed reads (16 rows per lane group)
+  // then fall in distinct banks
+  constexpr int RS = 65;
+  __shared__ double lamsh[4][32 * RS];
+  int mb, tile;
+  block_coords(ntiles, mb, tile);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = mb * 4 + wave;
+  const int L = a.lmax;
+  if (m > L) return;
+  const int mg = blockIdx.y;
+  if (a.skip.act) {
+    bool any = false;
+    for (int k = 0; k < 8 && mg * 8 + k < nmaps; ++k) any = any || !a.skip.off(mg * 8 + k);
+    if (!any) return;
+  }
+  double* lam = lamsh[wave];
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int p = tile * 64 + lane;
+  const bool valid = p < a.npairs;
+  const double z = valid ? a.zpair[p] : 0.0;
+  const int ls = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
+  const double2 st = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
+  // this lane's column: map mg * 8 + j / 2, part j & 1
+  const int j = i16;
+  const int map = mg * 8 + (j >> 1), cs = j & 1;
+  const bool colok = map < nmaps && !(m == 0 && cs == 1);
+  // B operands: H_E, H_O of pair tile*64 + 4 kb + kq in column j
+  double HE[16], HO[16];
+  {
+    const double* ph = reinterpret_cast<const double*>(phase + (int64_t)(colok ? map : 0) * pstride);
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) {
+      const int pp = tile * 64 + 4 * kb + kq;
+      double hn = 0.0, hs = 0.0;
+      const bool ok = colok && pp < a.npairs;
+      const int rs = a.nring - 1 - pp;
+      if (ok) {
+        hn = ph[2 * ((int64_t)pp * (L + 1) + m) + cs];
+        if (rs != pp) hs = ph[2 * ((int64_t)rs * (L + 1) + m) + cs];
+      }
+      // the equator ring is its own pair: lambda(z) H for both parities
+      HE[kb] = (ok && rs == pp) ? hn : hn + hs;
+      HO[kb] = (ok && rs == pp) ? hn : hn - hs;
+    }
+  }
+  const int nsl = L - m + 1;
+  double* const vb = vpart + (int64_t)tile * tstride + (int64_t)(colok ? map : 0) * vstride + moff(L, m) + cs * nsl - m;
+  const int lfirst = wave_min(ls);
+  int l0 = lfirst <= L ? lfirst - ((lfirst - m) & 1) : L + 1;
+  // zero partial below the first evaluated l
+  if (colok)
+    for (int l = m + kq; l < l0; l += 4) vb[l] = 0.0;
+  cdouble* gb = as_const(a.g + tri(L, m) - m);  // 8 zeros follow the table
+  double a0 = 0.0, a1 = 0.0;
+  int nx = lfirst;
+  for (int lb = l0; lb <= L; lb += 32) {
+    lb = __builtin_amdgcn_readfirstlane(lb);
+    const bool fast = nx >= lb + 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double gv[8];
+      cdouble* gp = gb + lb + 8 * q;
+      const bool in = lb + 8 * q <= L;  // groups past L are skipped (their rows are not written)
+      if (in) {
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) gv[s2] = gp[s2];
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) gv[s2] = 0.0;
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        const int l = lb + 8 * q + s2;
+        double cc = fma(gv[s2] * z, a1, -a0);
+        double pv = a1;
+        if (!fast && ls == l) {
+          cc = st.y;
+          pv = st.x;
+        }
+        a0 = pv;
+        a1 = cc;
+        lam[(8 * q + s2) * RS + lane] = cc;
+      }
+    }
+    if (!fast) nx = wave_min(ls >= lb + 32 ? ls : INT_MAX);
+    lds_wave_sync();
+    // four independent accumulator pairs (K-blocks kb = 4 u + v go to v)
+    v4d DE4[4], DO4[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      DE4[v] = v4d{0.0, 0.0, 0.0, 0.0};
+      DO4[v] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) {
+      const double aE = lam[(2 * i16) * RS + 4 * kb + kq];
+      const double aO = lam[(2 * i16 + 1) * RS + 4 * kb + kq];
+      DE4[kb & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, HE[kb], DE4[kb & 3], 0, 0, 0);
+      DO4[kb & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, HO[kb], DO4[kb & 3], 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const v4d DE = (DE4[0] + DE4[1]) + (DE4[2] + DE4[3]);
+    const v4d DO = (DO4[0] + DO4[1]) + (DO4[2] + DO4[3]);
+    // D[row = kq + 4 r][col = j]: l = lb + 2 row (E), lb + 2 row + 1 (O)
+    if (colok) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lE = lb + 2 * (kq + 4 * r);
+        if (lE <= L) vb[lE] = DE[r];
+        if (lE + 1 <= L) vb[lE + 1] = DO[r];
+      }
+    }
+  }
+}
+
 // -------------------------------------------------------- hat scaling
 // out[map][i] = c_m f_lm (or f_lm^2) * sum_t in[t][map][i]
 __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
@@ -551,9 +814,25 @@ static int syn_nm(int nmaps) {
   return best;
 }
 
+// Maps from which the synthesis uses the MFMA kernel (8 maps per wave);
+// CRS_LEG_MFMA_MIN overrides (tuning).
+static int mfma_min_maps() {
+  if (const char* e = std::getenv("CRS_LEG_MFMA_MIN")) return std::max(1, std::atoi(e));
+  return 4;
+}
+
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s) {
   const int L = a.lmax;
+  if (nmaps >= mfma_min_maps()) {
+    const int ntiles = (a.npairs + 63) / 64;
+    const int nmb = (L + 1 + 3) / 4;
+    const int nmb8 = (nmb + 7) / 8 * 8;
+    dim3 grid(nmb8 * ntiles, (nmaps + 7) / 8);
+    hipLaunchKernelGGL(k_leg_synth_mfma, grid, dim3(256), 0, s, a, nmaps, uhat, ustride, phase, pstride, ntiles);
+    CRS_HIP(hipGetLastError());
+    return;
+  }
   const int nm = syn_nm(nmaps);
   const int R = pick_r(a.npairs, L, std::max(1, 4 / nm), 1L << 40, "CRS_LEG_RS");
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
@@ -581,7 +860,10 @@ static int adj_nm(int nmaps, int R) {
   return std::min(nm, cap);
 }
 
-int leg_adjoint_tiles(int npairs, int L) {
+static bool adj_mfma(int nmaps, bool square) { return !square && nmaps >= mfma_min_maps(); }
+
+int leg_adjoint_tiles(int npairs, int L, int nmaps) {
+  if (adj_mfma(nmaps, false)) return (npairs + 63) / 64;
   const int R = adj_r(npairs, L);
   return (npairs + 64 * R - 1) / (64 * R);
 }
@@ -590,6 +872,16 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s) {
   const int L = a.lmax;
+  if (adj_mfma(nmaps, square)) {
+    const int ntiles = (a.npairs + 63) / 64;
+    const int nmb = (L + 1 + 3) / 4;
+    const int nmb8 = (nmb + 7) / 8 * 8;
+    dim3 grid(nmb8 * ntiles, (nmaps + 7) / 8);
+    hipLaunchKernelGGL(k_leg_adjoint_mfma, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride, tstride,
+                       ntiles);
+    CRS_HIP(hipGetLastError());
+    return;
+  }
   const int R = adj_r(a.npairs, L);
   const int nm = adj_nm(nmaps, R);
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
