@@ -634,18 +634,20 @@ __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const
 // v_par[l][col] = sum_p lambda_lm(p) H_par(p)[col] as a dense product: rows =
 // 16 values of l of one parity, K = ring pairs, N = 16 columns (8 maps x cos,
 // sin).  One wave owns (m, 64 ring pairs, 8 maps); lane t runs the recurrence
-// of pair t and writes each chunk of 32 steps [lb, lb + 32) (lb - m even) to a
-// wave-private LDS tile lam[32][64]; K-block kb (pairs 4 kb .. 4 kb + 3) then
-// feeds the MFMA with A lane (i, k) = lam[2 i (+1)][4 kb + k] and B lane
-// (j, k) = H_par(4 kb + k)[j] (held in registers: 16 K-blocks x E/O).  The
+// of pair t and writes each chunk of 32 steps [lb, lb + 32) (lb - m even) to
+// wave-private LDS tiles lamE / lamO [64 pairs][16 steps of one parity];
+// K-block kb (pairs 4 kb .. 4 kb + 3) then feeds the MFMA with A lane (i, k) =
+// lam_par[4 kb + k][i] and B lane (j, k) = H_par(4 kb + k)[j] (held in
+// registers: 16 K-blocks x E/O).  The
 // 16 x 16 results of a chunk are the wave's partial v for 32 values of l.
 __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                           int64_t pstride, double* __restrict__ vpart,
                                                           int64_t vstride, int64_t tstride, int ntiles) {
-  // rows padded to 65 doubles: the transposed reads (16 rows per lane group)
-  // then fall in distinct banks
-  constexpr int RS = 65;
-  __shared__ double lamsh[4][32 * RS];
+  // pair-major tiles per parity, lamE[pair][i] = lambda at l = lb + 2 i (O:
+  // + 1), rows of 17 doubles: a lane group's A reads (16 consecutive i) and
+  // the per-step writes (consecutive pairs, stride 17) are both conflict-free
+  constexpr int RS = 17;
+  __shared__ double lamsh[4][2 * 64 * RS];
   int mb, tile;
   block_coords(ntiles, mb, tile);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -658,7 +660,8 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
     for (int k = 0; k < 8 && mg * 8 + k < nmaps; ++k) any = any || !a.skip.off(mg * 8 + k);
     if (!any) return;
   }
-  double* lam = lamsh[wave];
+  double* lamE = lamsh[wave];
+  double* lamO = lamE + 64 * RS;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, kq = lane >> 4;
   const int p = tile * 64 + lane;
@@ -714,39 +717,48 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
 #pragma unroll
         for (int s2 = 0; s2 < 8; ++s2) gv[s2] = 0.0;
       }
+      if (fast) {
 #pragma unroll
-      for (int s2 = 0; s2 < 8; ++s2) {
-        const int l = lb + 8 * q + s2;
-        double cc = fma(gv[s2] * z, a1, -a0);
-        double pv = a1;
-        if (!fast && ls == l) {
-          cc = st.y;
-          pv = st.x;
+        for (int s2 = 0; s2 < 8; ++s2) {
+          const double cc = fma(gv[s2] * z, a1, -a0);
+          a0 = a1;
+          a1 = cc;
+          ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
         }
-        a0 = pv;
-        a1 = cc;
-        lam[(8 * q + s2) * RS + lane] = cc;
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+          double cc = fma(gv[s2] * z, a1, -a0);
+          double pv = a1;
+          if (ls == lb + 8 * q + s2) {
+            cc = st.y;
+            pv = st.x;
+          }
+          a0 = pv;
+          a1 = cc;
+          ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
+        }
       }
     }
     if (!fast) nx = wave_min(ls >= lb + 32 ? ls : INT_MAX);
     lds_wave_sync();
-    // four independent accumulator pairs (K-blocks kb = 4 u + v go to v)
-    v4d DE4[4], DO4[4];
+    // two independent accumulator pairs (even / odd K-blocks)
+    v4d DE2[2], DO2[2];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      DE4[v] = v4d{0.0, 0.0, 0.0, 0.0};
-      DO4[v] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < 2; ++v) {
+      DE2[v] = v4d{0.0, 0.0, 0.0, 0.0};
+      DO2[v] = v4d{0.0, 0.0, 0.0, 0.0};
     }
 #pragma unroll
     for (int kb = 0; kb < 16; ++kb) {
-      const double aE = lam[(2 * i16) * RS + 4 * kb + kq];
-      const double aO = lam[(2 * i16 + 1) * RS + 4 * kb + kq];
-      DE4[kb & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, HE[kb], DE4[kb & 3], 0, 0, 0);
-      DO4[kb & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, HO[kb], DO4[kb & 3], 0, 0, 0);
+      const double aE = lamE[(4 * kb + kq) * RS + i16];
+      const double aO = lamO[(4 * kb + kq) * RS + i16];
+      DE2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, HE[kb], DE2[kb & 1], 0, 0, 0);
+      DO2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, HO[kb], DO2[kb & 1], 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
-    const v4d DE = (DE4[0] + DE4[1]) + (DE4[2] + DE4[3]);
-    const v4d DO = (DO4[0] + DO4[1]) + (DO4[2] + DO4[3]);
+    const v4d DE = DE2[0] + DE2[1];
+    const v4d DO = DO2[0] + DO2[1];
     // D[row = kq + 4 r][col = j]: l = lb + 2 row (E), lb + 2 row + 1 (O)
     if (colok) {
 #pragma unroll
