@@ -40,10 +40,33 @@ __device__ __forceinline__ cdouble* as_const(const double* p) {
 // wave-uniform element (scalar load)
 __device__ __forceinline__ double uld(cdouble* p, int i) { return p[__builtin_amdgcn_readfirstlane(i)]; }
 
+// minimum over the wave's active lanes (DPP reduction, no LDS round trips)
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return __builtin_amdgcn_readfirstlane(v);
+  return __builtin_amdgcn_readfirstlane(__ockl_wfred_min_i32(v));
+}
+
+// v + v of lane t ^ 32 and v + v of lane t ^ 16, with the gfx950 lane-swap
+// instructions (v_permlane32_swap exchanges the upper half of its first
+// operand with the lower half of its second; v_permlane16_swap the odd rows of
+// the first with the even rows of the second): swapping v with itself leaves
+// the lane's own value in one result and the partner's in the other.
+__device__ __forceinline__ double add_xor32(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double x = __longlong_as_double((long long)(((uint64_t)b[0] << 32) | a[0]));
+  const double y = __longlong_as_double((long long)(((uint64_t)b[1] << 32) | a[1]));
+  return x + y;
+}
+__device__ __forceinline__ double add_xor16(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double x = __longlong_as_double((long long)(((uint64_t)b[0] << 32) | a[0]));
+  const double y = __longlong_as_double((long long)(((uint64_t)b[1] << 32) | a[1]));
+  return x + y;
 }
 
 __device__ __forceinline__ int64_t moff(int L, int m) {
@@ -56,10 +79,10 @@ __device__ __forceinline__ int64_t tri(int L, int m) {
 // ------------------------------------------------------- per-wave stepper
 // A wave owns R groups of 64 ring pairs: pair of group j on lane t is
 // base + 64 j + t (j = 0 most polar).  Per group the wave keeps the lanes'
-// recurrence state and two wave-uniform numbers: lw (first l any lane of the
-// group evaluates, forced non-increasing in j so that the groups running at
-// a given l are a suffix j >= q) and nx (next l where some lane of the group
-// starts).  Between start events all running groups step in lockstep.
+// recurrence state and two wave-uniform numbers: lw (first l any lane of
+// groups j..R-1 evaluates; lw[R-1] is where the wave starts stepping) and nx
+// (next l where some lane of the group starts).  Between start events all
+// groups step in lockstep; a lane before its start carries zero state.
 template <int R>
 struct Grp {
   double z[R], a0[R], a1[R];
@@ -84,34 +107,6 @@ __device__ __forceinline__ void grp_init(Grp<R>& G, const LegArgs& a, int m, int
     G.nx[j] = w;
     G.lw[j] = (j == 0) ? w : min(w, G.lw[j - 1]);
   }
-}
-
-// first running group at l (lw[R-1] <= l is required)
-template <int R>
-__device__ __forceinline__ int grp_first(const Grp<R>& G, int l) {
-  int q = R - 1;
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j)
-    if (G.lw[j] <= l) q = j;
-  return q;
-}
-
-template <int R>
-__device__ __forceinline__ int grp_next_event(const Grp<R>& G, int q) {
-  int ne = INT_MAX;
-#pragma unroll
-  for (int j = 0; j < R; ++j)
-    if (j >= q) ne = min(ne, G.nx[j]);
-  return ne;
-}
-
-template <int R>
-__device__ __forceinline__ int grp_next_start(const Grp<R>& G, int q, int L) {
-  int pe = L + 1;
-#pragma unroll
-  for (int j = 0; j < R; ++j)
-    if (j == q - 1) pe = G.lw[j];
-  return pe;
 }
 
 // One step of group j at l with start injection (event step).
@@ -252,25 +247,20 @@ __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, in
   for (int j = 0; j < R; ++j)
 #pragma unroll
     for (int k = 0; k < NM; ++k) A.X[j][k][0] = A.X[j][k][1] = A.Y[j][k][0] = A.Y[j][k][1] = 0.0;
+  // all R groups step from the first start of any of them (groups that have
+  // not started carry zero state and add zeros)
   int l = G.lw[R - 1];
   while (l <= L) {
-    const int q = grp_first<R>(G, l);
-    const int ne = grp_next_event<R>(G, q);
+    int ne = G.nx[0];
+#pragma unroll
+    for (int j = 1; j < R; ++j) ne = min(ne, G.nx[j]);
     if (ne == l) {
-      switch (R - q) {
-#define SYN_EV(NA) case NA: if (NA <= R) syn_event<NM, R, (NA <= R ? NA : R), HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l); break;
-        SYN_EV(1) SYN_EV(2) SYN_EV(3) SYN_EV(4)
-#undef SYN_EV
-      }
+      syn_event<NM, R, R, HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l);
       ++l;
       continue;
     }
-    const int stop = min(min(grp_next_start<R>(G, q, L), ne), L + 1);
-    switch (R - q) {
-#define SYN_PL(NA) case NA: if (NA <= R) syn_plain<NM, R, (NA <= R ? NA : R), HAS_S>(A, G, gb, ub, nsl, l, stop); break;
-      SYN_PL(1) SYN_PL(2) SYN_PL(3) SYN_PL(4)
-#undef SYN_PL
-    }
+    const int stop = min(ne, L + 1);
+    syn_plain<NM, R, R, HAS_S>(A, G, gb, ub, nsl, l, stop);
     l = stop;
   }
   // X holds parity (L + 1 - m) & 1 (the loop always ends at l = L + 1, or
@@ -307,7 +297,10 @@ __device__ __forceinline__ void block_coords(int ntiles, int& mb, int& tile) {
 }
 
 template <int NM, int R>
-__global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const double* __restrict__ uhat,
+#ifndef CRS_LEG_WAVES
+#define CRS_LEG_WAVES 1
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRS_LEG_WAVES))) void k_leg_synth(LegArgs a, int nmaps, const double* __restrict__ uhat,
                                                    int64_t ustride, double2* __restrict__ phase,
                                                    int64_t pstride, int ntiles) {
   int mb, tile;
@@ -474,20 +467,25 @@ struct AdjCfg {
   static constexpr int NOUT = CH * NM * 2;
 };
 
-template <int NM, int R, int NA, bool FAST, bool ODD0, bool SQ, bool HAS_S>
+// One chunk of CH steps [lc, lc + CH) for all R groups (lc - m even: even
+// steps use E, odd steps O).  Groups that have not started yet carry zero
+// state and contribute zeros.  FAST: no start event inside the chunk and all
+// CH steps <= L, so there are no per-step checks and P is initialised by the
+// first group's products.  Otherwise every step checks for start events and
+// the band-limit, and P must be zeroed by the caller.
+template <int NM, int R, bool FAST, bool SQ, bool HAS_S>
 __device__ __forceinline__ void adj_chunk(Grp<R>& G, const double (&E)[R][NM][2], const double (&O)[R][NM][2],
                                           const double (&gv)[AdjCfg<NM>::CH], const LegArgs& a, int m,
                                           int base, int lane, int lc, int L,
                                           double (&P)[AdjCfg<NM>::CH][NM][2]) {
   constexpr int CH = AdjCfg<NM>::CH;
-  constexpr int J0 = R - NA;
 #pragma unroll
   for (int s = 0; s < CH; ++s) {
     const int l = lc + s;
-    if (l > L) break;
-    const bool odd = ODD0 ^ ((s & 1) != 0);
+    if (!FAST && l > L) break;
+    const bool odd = (s & 1) != 0;
 #pragma unroll
-    for (int j = J0; j < R; ++j) {
+    for (int j = 0; j < R; ++j) {
       double c;
       if (FAST) {
         c = fma(gv[s] * G.z[j], G.a1[j], -G.a0[j]);
@@ -499,8 +497,15 @@ __device__ __forceinline__ void adj_chunk(Grp<R>& G, const double (&E)[R][NM][2]
       const double w = SQ ? c * c : c;
 #pragma unroll
       for (int k = 0; k < NM; ++k) {
-        P[s][k][0] = fma(w, (SQ || !odd) ? E[j][k][0] : O[j][k][0], P[s][k][0]);
-        if (HAS_S) P[s][k][1] = fma(w, (SQ || !odd) ? E[j][k][1] : O[j][k][1], P[s][k][1]);
+        const double hc = (SQ || !odd) ? E[j][k][0] : O[j][k][0];
+        const double hs = (SQ || !odd) ? E[j][k][1] : O[j][k][1];
+        if (FAST && j == 0) {
+          P[s][k][0] = w * hc;
+          P[s][k][1] = HAS_S ? w * hs : 0.0;
+        } else {
+          P[s][k][0] = fma(w, hc, P[s][k][0]);
+          if (HAS_S) P[s][k][1] = fma(w, hs, P[s][k][1]);
+        }
       }
     }
   }
@@ -514,6 +519,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
   constexpr int CH = AdjCfg<NM>::CH;
   constexpr int NOUT = AdjCfg<NM>::NOUT;
   static_assert(NOUT == 16, "wave reduction assumes 16 outputs per chunk");
+  static_assert(CH % 2 == 0, "chunks keep the parity of their first step");
   const int L = a.lmax;
   const int base = tile * 64 * R;
   cdouble* gb = as_const(a.g + tri(L, m) - m);
@@ -543,9 +549,12 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
   }
   const int nsl = L - m + 1;
   double* const vbase = vpart + (int64_t)tile * tstride + moff(L, m);
+  // first evaluated l of any group, moved down to the parity of m (the step
+  // before a start produces zeros)
   int l0 = G.lw[R - 1];
   if (l0 < m) l0 = m;
   if (l0 > L + 1) l0 = L + 1;
+  l0 -= (l0 - m) & 1;
   // zero-fill this tile's output below the first evaluated l
   for (int i = lane; i < (l0 - m) * NM * 2; i += 64) {
     const int nl = l0 - m;
@@ -554,34 +563,27 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
     vbase[(int64_t)(map0 + k) * vstride + cs * nsl + ll] = 0.0;
   }
   for (int lc = l0; lc <= L; lc += CH) {
-    const int lend = min(lc + CH - 1, L);
-    const int q = grp_first<R>(G, lend);
-    const bool fast = grp_next_event<R>(G, q) > lend;
-    const bool odd0 = ((lc - m) & 1) != 0;
+    const int lend = lc + CH - 1;
+    int ne = G.nx[0];
+#pragma unroll
+    for (int j = 1; j < R; ++j) ne = min(ne, G.nx[j]);
+    const bool fast = ne > lend && lend <= L;
+    // g of m is followed by g of m + 1 (and the table by 8 zeros), so the CH
+    // values from lc are always in bounds; those past L go unused
     double gv[CH];
     cdouble* gp = gb + __builtin_amdgcn_readfirstlane(lc);
 #pragma unroll
-    for (int s = 0; s < CH; ++s) gv[s] = (lc + s <= L) ? gp[s] : 0.0;
+    for (int s = 0; s < CH; ++s) gv[s] = gp[s];
     double P[CH][NM][2];
+    if (fast) {
+      adj_chunk<NM, R, true, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);
+    } else {
 #pragma unroll
-    for (int s = 0; s < CH; ++s)
+      for (int s = 0; s < CH; ++s)
 #pragma unroll
-      for (int k = 0; k < NM; ++k) P[s][k][0] = P[s][k][1] = 0.0;
-#define ADJ_CASE(NA)                                                                                  \
-  case NA:                                                                                            \
-    if (NA <= R) {                                                                                    \
-      constexpr int NAc = NA <= R ? NA : R;                                                           \
-      if (fast) {                                                                                     \
-        if (odd0) adj_chunk<NM, R, NAc, true, true, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);   \
-        else adj_chunk<NM, R, NAc, true, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);       \
-      } else {                                                                                        \
-        if (odd0) adj_chunk<NM, R, NAc, false, true, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);  \
-        else adj_chunk<NM, R, NAc, false, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);      \
-      }                                                                                               \
-    }                                                                                                 \
-    break;
-    switch (R - q) { ADJ_CASE(1) ADJ_CASE(2) ADJ_CASE(3) ADJ_CASE(4) }
-#undef ADJ_CASE
+        for (int k = 0; k < NM; ++k) P[s][k][0] = P[s][k][1] = 0.0;
+      adj_chunk<NM, R, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);
+    }
     // wave-private reduction: wb is [NOUT][65]
 #pragma unroll
     for (int s = 0; s < CH; ++s)
@@ -595,8 +597,8 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc += wb[o * 65 + sub + 4 * i];
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
+    acc = add_xor16(acc);
+    acc = add_xor32(acc);
     __builtin_amdgcn_wave_barrier();
     if (sub == 0) {
       const int s = o / (NM * 2), k = (o >> 1) % NM, cs = o & 1;
@@ -608,7 +610,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
 }
 
 template <int NM, int R, bool SQ>
-__global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRS_LEG_WAVES))) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                      int64_t pstride, double* __restrict__ vpart,
                                                      int64_t vstride, int64_t tstride, int ntiles) {
   __shared__ double wbuf[4][AdjCfg<NM>::NOUT * 65];
@@ -802,10 +804,10 @@ __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
 // synthesis is fastest at R = 1 throughout, the adjoint at R = 2 once that
 // leaves >= 4096 waves.  The environment variables CRS_LEG_RS and
 // CRS_LEG_RA fix R for synthesis and adjoint (tuning).
-static int pick_r(int npairs, int L, int rmax, long want, const char* env) {
+static int pick_r(int npairs, int L, int rmax, long want, const char* env, int envmax) {
   if (const char* e = std::getenv(env)) {
     const int r = std::atoi(e);
-    if (r == 1 || r == 2 || r == 4) return std::min(r, rmax);
+    if (r == 1 || r == 2 || r == 4) return std::min(r, envmax);
   }
   for (int R : {4, 2, 1}) {
     if (R > rmax) continue;
@@ -846,7 +848,7 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
     return;
   }
   const int nm = syn_nm(nmaps);
-  const int R = pick_r(a.npairs, L, std::max(1, 4 / nm), 1L << 40, "CRS_LEG_RS");
+  const int R = pick_r(a.npairs, L, std::max(1, 4 / nm), 1L << 40, "CRS_LEG_RS", std::max(1, 4 / nm));
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
@@ -864,7 +866,7 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
 // The adjoint's ring tile count depends on (npairs, L) only, so that the
 // partial-sum buffers and their consumers do not depend on the map count:
 // R is chosen first and the maps per wave follow (R * NM <= 8).
-static int adj_r(int npairs, int L) { return pick_r(npairs, L, 2, 4096, "CRS_LEG_RA"); }
+static int adj_r(int npairs, int L) { return pick_r(npairs, L, 4, 4096, "CRS_LEG_RA", 4); }
 
 static int adj_nm(int nmaps, int R) {
   const int cap = 8 / R;
