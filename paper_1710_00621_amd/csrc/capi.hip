@@ -277,7 +277,7 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
     const int64_t pst = (int64_t)g->nring * (lmax + 1);
     w.uhat.alloc((size_t)nmaps * nalm);
     w.phase.alloc((size_t)nmaps * pst);
-    launch_hat_scale(p.f.p, lmax, nmaps, alm, alm_stride, 1, 0, w.uhat.p, nalm, false, s);
+    launch_tile_sum(p.hs.p, nalm, nmaps, alm, alm_stride, 1, 0, w.uhat.p, nalm, s);
     {
       ProfScope ps(FAM_LEG_SYNTH, leg_flops(p, nmaps), s);
       launch_leg_synth(leg_args(g, p), nmaps, w.uhat.p, nalm, w.phase.p, pst, s);
@@ -303,7 +303,7 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     GridWork& w = *g->work;
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
     const int64_t pst = (int64_t)g->nring * (lmax + 1);
-    const int ntiles = leg_adjoint_tiles(p.npairs, lmax, nmaps);
+    const int ntiles = leg_adjoint_tiles(p.npairs, lmax, nmaps, false);
     w.phase.alloc((size_t)nmaps * pst);
     w.vpart.alloc((size_t)ntiles * nmaps * nalm);
     {
@@ -316,8 +316,7 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
       launch_leg_adjoint(leg_args(g, p), nmaps, w.phase.p, pst, w.vpart.p, nalm,
                          (int64_t)nmaps * nalm, false, s);
     }
-    launch_hat_scale(p.f.p, lmax, nmaps, w.vpart.p, nalm, ntiles, (int64_t)nmaps * nalm, alm,
-                     alm_stride, false, s);
+    launch_tile_sum(p.hs.p, nalm, nmaps, w.vpart.p, nalm, ntiles, (int64_t)nmaps * nalm, alm, alm_stride, s);
     return CRS_OK;
   });
 }

@@ -421,7 +421,7 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   }
   for (auto& g : e->groups) {
     g.plan = &get_plan(g.grid, g.lmax, s);
-    g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax, g.nmaps);
+    g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax, g.nmaps, false);
     g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
     g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
     std::vector<const double*> wa, wp, ta;

@@ -430,8 +430,20 @@ ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s) {
       pme[m] = (int)ee;
     }
   }
+  // c_m f_lm in the packed alm layout ([m = 0: l], then per m >= 1 [cos: l][sin: l])
+  std::vector<double> hs((size_t)(L + 1) * (L + 1));
+  {
+    size_t o = 0;
+    for (int m = 0; m <= L; ++m) {
+      const double cm = m == 0 ? 1.0 : std::sqrt(2.0);
+      const int64_t t = tri_off(L, m) - m;
+      for (int part = 0; part < (m == 0 ? 1 : 2); ++part)
+        for (int l = m; l <= L; ++l) hs[o++] = cm * ft[t + l];
+    }
+  }
   plan->g.upload(gt, s);
   plan->f.upload(ft, s);
+  plan->hs.upload(hs, s);
   DevBuf<double> dpm;
   DevBuf<int> dpe;
   dpm.upload(pmm, s);

@@ -106,6 +106,7 @@ struct ShtPlan {
   int64_t nominal_triples = 0; // npairs * (L+1)(L+2)/2
   DevBuf<double> g;            // triangle: g_lm, mu recurrence coefficient
   DevBuf<double> f;            // triangle: f_lm, lambda = f * mu
+  DevBuf<double> hs;           // packed alm layout: c_m f_lm (plain <-> hat vectors)
   DevBuf<int> ls;              // [L+1][npairs]: first l evaluated (L+1 = never)
   DevBuf<double2> ms;          // [L+1][npairs]: (mu_{ls-1}, mu_ls)
   std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
@@ -184,8 +185,9 @@ struct LegArgs {
 // phase: [nmaps][nring][L+1] double2 (cos, sin parts)
 void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s);
-// Adjoint: writes ntiles partial vectors vpart[tile][map][nalm]; returns ntiles.
-int leg_adjoint_tiles(int npairs, int lmax, int nmaps);
+// Adjoint: writes ntiles partial vectors vpart[tile][map][nalm], ntiles as
+// returned here for the same (nmaps, square) as the launch.
+int leg_adjoint_tiles(int npairs, int lmax, int nmaps, bool square);
 void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s);
@@ -217,7 +219,12 @@ void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase,
                  const double* const* weights, int maps_per_weight, hipStream_t s,
                  MapSkip skip = MapSkip{});
 
-// Scaling between plain and hat vectors: out = c_m f_lm in (+ sum over tiles).
+// Scaling between plain and hat vectors: out[map] = hs * sum_t in[t][map]
+// elementwise over the packed alm index (hs = c_m f_lm, ShtPlan::hs).
+void launch_tile_sum(const double* hs, int64_t nalm, int nmaps, const double* in, int64_t istride,
+                     int ntiles, int64_t tstride, double* out, int64_t ostride, hipStream_t s);
+// Same with the scale computed per (l, m) from the f triangle; square: f^2
+// without c_m (the M_diag setup).
 void launch_hat_scale(const double* f, int lmax, int nmaps, const double* in, int64_t istride,
                       int ntiles, int64_t tstride, double* out, int64_t ostride, bool square,
                       hipStream_t s);

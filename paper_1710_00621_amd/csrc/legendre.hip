@@ -635,23 +635,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRS_LEG_WAV
 // -------------------------------------------------------- adjoint, MFMA
 // v_par[l][col] = sum_p lambda_lm(p) H_par(p)[col] as a dense product: rows =
 // 16 values of l of one parity, K = ring pairs, N = 16 columns (8 maps x cos,
-// sin).  One wave owns (m, 64 ring pairs, 8 maps); lane t runs the recurrence
-// of pair t and writes each chunk of 32 steps [lb, lb + 32) (lb - m even) to
-// wave-private LDS tiles lamE / lamO [64 pairs][16 steps of one parity];
-// K-block kb (pairs 4 kb .. 4 kb + 3) then feeds the MFMA with A lane (i, k) =
-// lam_par[4 kb + k][i] and B lane (j, k) = H_par(4 kb + k)[j] (held in
-// registers: 16 K-blocks x E/O).  The
-// 16 x 16 results of a chunk are the wave's partial v for 32 values of l.
+// sin).  One wave owns (m, T tiles of 64 ring pairs, 8 maps); lane t runs the
+// recurrences of pair t of each tile and, tile after tile, writes each chunk
+// of 32 steps [lb, lb + 32) (lb - m even) to wave-private LDS tiles lamE /
+// lamO [64 pairs][16 steps of one parity]; K-block kb (pairs 4 kb .. 4 kb + 3)
+// then feeds the MFMA with A lane (i, k) = lam_par[4 kb + k][i] and B lane
+// (j, k) = H_par(4 kb + k)[j] (held in registers: T tiles x 16 K-blocks x
+// E/O).  The T tiles accumulate into the same 16 x 16 results, the wave's
+// partial v for 32 values of l: one partial per T tiles, T times less
+// partial-sum traffic to and from HBM than one per tile.
+template <int T>
 __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                           int64_t pstride, double* __restrict__ vpart,
-                                                          int64_t vstride, int64_t tstride, int ntiles) {
+                                                          int64_t vstride, int64_t tstride, int ntg) {
   // pair-major tiles per parity, lamE[pair][i] = lambda at l = lb + 2 i (O:
   // + 1), rows of 17 doubles: a lane group's A reads (16 consecutive i) and
   // the per-step writes (consecutive pairs, stride 17) are both conflict-free
   constexpr int RS = 17;
   __shared__ double lamsh[4][2 * 64 * RS];
-  int mb, tile;
-  block_coords(ntiles, mb, tile);
+  int mb, tg;
+  block_coords(ntg, mb, tg);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int m = mb * 4 + wave;
   const int L = a.lmax;
@@ -666,18 +669,27 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
   double* lamO = lamE + 64 * RS;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int p = tile * 64 + lane;
-  const bool valid = p < a.npairs;
-  const double z = valid ? a.zpair[p] : 0.0;
-  const int ls = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
-  const double2 st = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
   // this lane's column: map mg * 8 + j / 2, part j & 1
   const int j = i16;
   const int map = mg * 8 + (j >> 1), cs = j & 1;
   const bool colok = map < nmaps && !(m == 0 && cs == 1);
-  // B operands: H_E, H_O of pair tile*64 + 4 kb + kq in column j
-  double HE[16], HO[16];
-  {
+  double z[T], a0[T], a1[T];
+  double2 st[T];
+  int ls[T], nx[T];
+  // B operands: H_E, H_O of pair (tg T + t) 64 + 4 kb + kq in column j
+  double HE[T][16], HO[T][16];
+  int lfirst = INT_MAX;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int tile = tg * T + t;
+    const int p = tile * 64 + lane;
+    const bool valid = p < a.npairs;
+    z[t] = valid ? a.zpair[p] : 0.0;
+    ls[t] = valid ? a.ls[(size_t)m * a.npairs + p] : INT_MAX;
+    st[t] = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
+    a0[t] = a1[t] = 0.0;
+    nx[t] = wave_min(ls[t]);
+    lfirst = min(lfirst, nx[t]);
     const double* ph = reinterpret_cast<const double*>(phase + (int64_t)(colok ? map : 0) * pstride);
 #pragma unroll
     for (int kb = 0; kb < 16; ++kb) {
@@ -690,60 +702,19 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
         if (rs != pp) hs = ph[2 * ((int64_t)rs * (L + 1) + m) + cs];
       }
       // the equator ring is its own pair: lambda(z) H for both parities
-      HE[kb] = (ok && rs == pp) ? hn : hn + hs;
-      HO[kb] = (ok && rs == pp) ? hn : hn - hs;
+      HE[t][kb] = (ok && rs == pp) ? hn : hn + hs;
+      HO[t][kb] = (ok && rs == pp) ? hn : hn - hs;
     }
   }
   const int nsl = L - m + 1;
-  double* const vb = vpart + (int64_t)tile * tstride + (int64_t)(colok ? map : 0) * vstride + moff(L, m) + cs * nsl - m;
-  const int lfirst = wave_min(ls);
-  int l0 = lfirst <= L ? lfirst - ((lfirst - m) & 1) : L + 1;
+  double* const vb = vpart + (int64_t)tg * tstride + (int64_t)(colok ? map : 0) * vstride + moff(L, m) + cs * nsl - m;
+  const int l0 = lfirst <= L ? lfirst - ((lfirst - m) & 1) : L + 1;
   // zero partial below the first evaluated l
   if (colok)
     for (int l = m + kq; l < l0; l += 4) vb[l] = 0.0;
   cdouble* gb = as_const(a.g + tri(L, m) - m);  // 8 zeros follow the table
-  double a0 = 0.0, a1 = 0.0;
-  int nx = lfirst;
   for (int lb = l0; lb <= L; lb += 32) {
     lb = __builtin_amdgcn_readfirstlane(lb);
-    const bool fast = nx >= lb + 32;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double gv[8];
-      cdouble* gp = gb + lb + 8 * q;
-      const bool in = lb + 8 * q <= L;  // groups past L are skipped (their rows are not written)
-      if (in) {
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) gv[s2] = gp[s2];
-      } else {
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) gv[s2] = 0.0;
-      }
-      if (fast) {
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) {
-          const double cc = fma(gv[s2] * z, a1, -a0);
-          a0 = a1;
-          a1 = cc;
-          ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
-        }
-      } else {
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) {
-          double cc = fma(gv[s2] * z, a1, -a0);
-          double pv = a1;
-          if (ls == lb + 8 * q + s2) {
-            cc = st.y;
-            pv = st.x;
-          }
-          a0 = pv;
-          a1 = cc;
-          ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
-        }
-      }
-    }
-    if (!fast) nx = wave_min(ls >= lb + 32 ? ls : INT_MAX);
-    lds_wave_sync();
     // two independent accumulator pairs (even / odd K-blocks)
     v4d DE2[2], DO2[2];
 #pragma unroll
@@ -752,13 +723,52 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
       DO2[v] = v4d{0.0, 0.0, 0.0, 0.0};
     }
 #pragma unroll
-    for (int kb = 0; kb < 16; ++kb) {
-      const double aE = lamE[(4 * kb + kq) * RS + i16];
-      const double aO = lamO[(4 * kb + kq) * RS + i16];
-      DE2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, HE[kb], DE2[kb & 1], 0, 0, 0);
-      DO2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, HO[kb], DO2[kb & 1], 0, 0, 0);
+    for (int t = 0; t < T; ++t) {
+      const bool fast = nx[t] >= lb + 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // groups of 8 steps that start past L are not loaded (their rows are
+        // never stored)
+        double gv[8];
+        cdouble* gp = gb + lb + 8 * q;
+        const bool in = lb + 8 * q <= L;
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) gv[s2] = in ? gp[s2] : 0.0;
+        if (fast) {
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2) {
+            const double cc = fma(gv[s2] * z[t], a1[t], -a0[t]);
+            a0[t] = a1[t];
+            a1[t] = cc;
+            ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
+          }
+        } else {
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2) {
+            double cc = fma(gv[s2] * z[t], a1[t], -a0[t]);
+            double pv = a1[t];
+            if (ls[t] == lb + 8 * q + s2) {
+              cc = st[t].y;
+              pv = st[t].x;
+            }
+            a0[t] = pv;
+            a1[t] = cc;
+            ((s2 & 1) ? lamO : lamE)[lane * RS + 4 * q + (s2 >> 1)] = cc;
+          }
+        }
+      }
+      if (!fast) nx[t] = wave_min(ls[t] >= lb + 32 ? ls[t] : INT_MAX);
+      lds_wave_sync();
+#pragma unroll
+      for (int kb = 0; kb < 16; ++kb) {
+        const double aE = lamE[(4 * kb + kq) * RS + i16];
+        const double aO = lamO[(4 * kb + kq) * RS + i16];
+        DE2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE, HE[t][kb], DE2[kb & 1], 0, 0, 0);
+        DO2[kb & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO, HO[t][kb], DO2[kb & 1], 0, 0, 0);
+      }
+      // the next tile's (or chunk's) steps overwrite lam only after these reads
+      lds_wave_sync();
     }
-    __builtin_amdgcn_wave_barrier();
     const v4d DE = DE2[0] + DE2[1];
     const v4d DO = DO2[0] + DO2[1];
     // D[row = kq + 4 r][col = j]: l = lb + 2 row (E), lb + 2 row + 1 (O)
@@ -876,8 +886,19 @@ static int adj_nm(int nmaps, int R) {
 
 static bool adj_mfma(int nmaps, bool square) { return !square && nmaps >= mfma_min_maps(); }
 
-int leg_adjoint_tiles(int npairs, int L, int nmaps) {
-  if (adj_mfma(nmaps, false)) return (npairs + 63) / 64;
+// 64-pair tiles per wave of the MFMA adjoint: two once that still leaves
+// >= 4096 waves (CRS_LEG_TA fixes it: tuning)
+static int adj_mfma_t(int npairs, int L) {
+  if (const char* e = std::getenv("CRS_LEG_TA")) return std::atoi(e) == 2 ? 2 : 1;
+  const long nt = (npairs + 63) / 64;
+  return (long)(L + 1) * ((nt + 1) / 2) >= 4096 ? 2 : 1;
+}
+
+int leg_adjoint_tiles(int npairs, int L, int nmaps, bool square) {
+  if (adj_mfma(nmaps, square)) {
+    const int t = adj_mfma_t(npairs, L);
+    return ((npairs + 63) / 64 + t - 1) / t;
+  }
   const int R = adj_r(npairs, L);
   return (npairs + 64 * R - 1) / (64 * R);
 }
@@ -887,12 +908,16 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
                         hipStream_t s) {
   const int L = a.lmax;
   if (adj_mfma(nmaps, square)) {
-    const int ntiles = (a.npairs + 63) / 64;
+    const int ntg = leg_adjoint_tiles(a.npairs, L, nmaps, square);
     const int nmb = (L + 1 + 3) / 4;
     const int nmb8 = (nmb + 7) / 8 * 8;
-    dim3 grid(nmb8 * ntiles, (nmaps + 7) / 8);
-    hipLaunchKernelGGL(k_leg_adjoint_mfma, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride, tstride,
-                       ntiles);
+    dim3 grid(nmb8 * ntg, (nmaps + 7) / 8);
+    if (adj_mfma_t(a.npairs, L) == 2)
+      hipLaunchKernelGGL(k_leg_adjoint_mfma<2>, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride,
+                         tstride, ntg);
+    else
+      hipLaunchKernelGGL(k_leg_adjoint_mfma<1>, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride,
+                         tstride, ntg);
     CRS_HIP(hipGetLastError());
     return;
   }
@@ -918,6 +943,28 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
   CRS_ADJ(4, 1) CRS_ADJ(4, 2)
 #undef CRS_ADJ
   throw Error{CRS_EINVAL, "no adjoint kernel variant"};
+}
+
+namespace {
+__global__ void k_tile_sum(const double* __restrict__ hs, int64_t nalm, const double* __restrict__ in,
+                           int64_t istride, int ntiles, int64_t tstride, double* __restrict__ out,
+                           int64_t ostride) {
+  const int map = blockIdx.y;
+  const double* __restrict__ src = in + (int64_t)map * istride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < ntiles; ++t) acc += src[(int64_t)t * tstride + i];
+    out[(int64_t)map * ostride + i] = hs[i] * acc;
+  }
+}
+}  // namespace
+
+void launch_tile_sum(const double* hs, int64_t nalm, int nmaps, const double* in, int64_t istride,
+                     int ntiles, int64_t tstride, double* out, int64_t ostride, hipStream_t s) {
+  const int64_t nb = std::min<int64_t>((nalm + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)nb, nmaps), dim3(256), 0, s, hs, nalm, in, istride, ntiles, tstride,
+                     out, ostride);
+  CRS_HIP(hipGetLastError());
 }
 
 void launch_hat_scale(const double* f, int lmax, int nmaps, const double* in, int64_t istride,

@@ -203,7 +203,7 @@ void build_diag(crs_model m, hipStream_t s) {
   for (int nu = 0; nu < nb; ++nu) {
     Band& b = m->bands[nu];
     ShtPlan& p = get_plan(b.grid, b.lmax, s);
-    const int ntiles = leg_adjoint_tiles(p.npairs, b.lmax, 1);
+    const int ntiles = leg_adjoint_tiles(p.npairs, b.lmax, 1, true);
     const int64_t nalm = (int64_t)(b.lmax + 1) * (b.lmax + 1);
     const int64_t pst = (int64_t)b.grid->nring * (b.lmax + 1);
     DevBuf<double2> ph;
