@@ -34,6 +34,11 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X published dense FP64 (vector and matrix)
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel family, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes over this benchmark (scaled by a plain copy of known size);
+# used only while the Legendre source is the one the counters were taken on
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "legendre_adjoint_batched_cr64_traffic.txt")
+LEGENDRE_SRC = os.path.join(ROOT, "paper_1710_00621_amd", "csrc", "legendre.hip")
 
 
 def log(*a):
@@ -190,6 +195,28 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
                        f"count; extrapolated per RHS")}
 
 
+def _traffic(kernel):
+    import hashlib
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            text = fh.read()
+        with open(LEGENDRE_SRC, "rb") as fh:
+            sha = hashlib.sha1(fh.read()).hexdigest()
+    except OSError:
+        return None
+    f = {}
+    for line in text.splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            f[k.strip()] = v.strip()
+    if f.get("kernel") != kernel or f.get("legendre_source_sha1") != sha:
+        return None
+    try:
+        return float(f["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _roofline(crsolve, ms_total):
     fam = {f: crsolve.kernel_stats(f) for f in ("legendre_synth", "legendre_adjoint", "ring_fft")}
     dom = max(("legendre_synth", "legendre_adjoint"), key=lambda f: fam[f]["ms"])
@@ -197,7 +224,7 @@ def _roofline(crsolve, ms_total):
     achieved = st["work"] / max(1e-30, st["ms"] * 1e-3) / 1e12
     ring = fam["ring_fft"]
     return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": _traffic(dom),
             "avg_launch_ms": st["ms"] / max(1, st["launches"]), "launches": st["launches"],
             "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
             / max(1e-9, ms_total),
@@ -229,6 +256,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sht-roofline", action="store_true")
     ap.add_argument("--no-multires", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workload: skip the plain (one solve per problem) pass and the "
+                         "pseudo-inverse sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a dispatch of known "
                          "traffic for scaling hardware byte counters)")
@@ -251,7 +281,7 @@ def main():
         nel = a.copy_probe_mb * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # one elementwise kernel: reads and writes copy_probe_mb MiB
         torch.cuda.synchronize()
         del src, dst
     t0 = time.time()
@@ -269,7 +299,8 @@ def main():
         for w in range(a.warmup):
             it = batch_solve(batch, probs, a.precond, a.rtol, a.maxiter)
             log(f"warmup {w}: batched iterations max {max(it)}")
-            it_p = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
+            if not a.no_plain:
+                solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
         torch.cuda.synchronize()
         crsolve.kernel_stats_reset()
         crsolve.set_profiling(True)
@@ -283,6 +314,9 @@ def main():
         per_rhs = ms_per_step / nrhs
         roof = _roofline(crsolve, ms_per_step * a.steps)
         log(f"batched: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+        mode = (f"batched: one stacked PCG over all {nrhs} problems, each iteration one captured "
+                f"hipGraph")
+    if a.workload == "batched" and not a.no_plain:
         # plain: the same problems one constrained_realization call at a time, no graphs
         torch.cuda.synchronize()
         tp = time.perf_counter()
@@ -290,8 +324,7 @@ def main():
         torch.cuda.synchronize()
         plain_rhs = (time.perf_counter() - tp) * 1e3 / nrhs
         log(f"plain: {plain_rhs:.3f} ms/RHS")
-        mode = (f"batched: one stacked PCG over all {nrhs} problems, each iteration one captured "
-                f"hipGraph; plain = {nrhs} separate constrained_realization calls without graphs")
+        mode += f"; plain = {nrhs} separate constrained_realization calls without graphs"
         extra["plain_ms_per_rhs"] = plain_rhs
         extra["speedup_batched_over_plain"] = plain_rhs / per_rhs
         extra["plain_iterations_sum"] = int(sum(it_p))
@@ -308,7 +341,7 @@ def main():
                 "relres": info["relres"][0], "ms": (time.perf_counter() - tq) * 1e3,
                 "note": "pseudo-inverse preconditioner under a mask (tau^+ = 0 there), maxiter 3000"}
             log(f"pinv sample: {extra['pinv_sample']}")
-    else:
+    elif a.workload != "batched":
         for w in range(a.warmup):
             it = solve_all(probs, a.precond, a.rtol, a.maxiter, torch)
             log(f"warmup {w}: iterations {it}")
