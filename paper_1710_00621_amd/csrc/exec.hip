@@ -37,22 +37,23 @@ enum { S_RHO = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_ACTIVE = 4, S_BREAK = 5, 
 
 // ---------------------------------------------------------------- kernels
 // uhat[map][i] = c_m f_lm sum_k coef[l][band][k] x[sys][coff_k + idx_k]
+// (grid: packed-index blocks of kWorkBlock x maps)
 __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict__ sys,
                           const ProbDev* __restrict__ probs, const SlotDev* __restrict__ slots, int usep,
                           int Lb, double* __restrict__ uhat, int64_t nalm, const double* __restrict__ act) {
-  const int m = blockIdx.y;
-  const int map = blockIdx.z;
+  const int map = blockIdx.y;
   const SlotDev sl = slots[map];
   if (act && act[kScal * sl.sys] == 0.0) return;
   const SysDev S = sys[sl.sys];
   const ProbDev P = probs[S.prob];
   const double* __restrict__ coef = usep ? P.cP : P.cA;
   const double* __restrict__ xs = x + S.off;
-  const int nsl = Lb - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
+  const int64_t i0 = (int64_t)blockIdx.x * kWorkBlock;
+  const int64_t i1 = min(nalm, i0 + kWorkBlock);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    int m, part, ll;
+    unpack_lm(Lb, i, m, part, ll);
+    const int l = m + ll;
     double acc = 0.0;
     for (int k = 0; k < P.nc; ++k) {
       const int L = P.lk[k];
@@ -61,36 +62,36 @@ __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict
       const int64_t idx = P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
       acc = fma(c, xs[idx], acc);
     }
-    uhat[(int64_t)map * nalm + moff_h(Lb, m) + i] = cm * P.ftab[tri_h(P.Lf, m) + ll] * acc;
+    const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
+    uhat[(int64_t)map * nalm + i] = cm * P.ftab[tri_h(P.Lf, m) + ll] * acc;
   }
 }
 
 // y[sys][coff_k + idx] = diag term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
 // dmode 0: no diag term; 1: (dsqrt ? C^-1/2 : C^-1) din; 2: Pi_l din.
+// (grid: one block per work-list entry over the (system, component) rows)
 __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ din,
                            const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
-                           const int2* __restrict__ rows, int dmode, int dsqrt, int usep,
-                           const double* __restrict__ act) {
-  const int m = blockIdx.y;
-  const int2 row = rows[blockIdx.z];
+                           const int2* __restrict__ rows, const int4* __restrict__ wl, int dmode, int dsqrt,
+                           int usep, const double* __restrict__ act) {
+  const int4 w = wl[blockIdx.x];
+  const int2 row = rows[w.x];
   if (act && act[kScal * row.x] == 0.0) return;
   const SysDev S = sys[row.x];
   const ProbDev P = probs[S.prob];
   const int k = row.y;
   const int Lk = P.lk[k];
-  if (m > Lk) return;
   const int nc = P.nc;
   const double* __restrict__ coef = usep ? P.cP : P.cA;
   const double* __restrict__ ds = din ? din + S.off : nullptr;
-  const int nsl = Lk - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
+  for (int i = w.y + threadIdx.x; i < w.z; i += blockDim.x) {
+    int m, part, ll;
+    unpack_lm(Lk, i, m, part, ll);
+    const int l = m + ll;
     double acc = 0.0;
     if (dmode == 1) {
       const double* dt = dsqrt ? P.dSqrt : P.dInv;
-      acc = dt[(int64_t)l * nc + k] * ds[P.coff[k] + moff_h(Lk, m) + i];
+      acc = dt[(int64_t)l * nc + k] * ds[P.coff[k] + i];
     } else if (dmode == 2) {
       for (int kp = 0; kp < nc; ++kp) {
         const int Lp = P.lk[kp];
@@ -99,6 +100,7 @@ __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ di
                   ds[P.coff[kp] + moff_h(Lp, m) + (int64_t)part * (Lp - m + 1) + ll], acc);
       }
     }
+    const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
     const double fs = cm * P.ftab[tri_h(P.Lf, m) + ll];
     for (int nu = 0; nu < P.nb; ++nu) {
       const int* bi = P.binfo + 5 * nu;
@@ -108,29 +110,29 @@ __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ di
       const int64_t nalm = (int64_t)(L + 1) * (L + 1);
       const int64_t tstride = (int64_t)gmaps * nalm;
       const double* v = P.vptr[nu] + (int64_t)map * nalm + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
-      double s = 0.0;
-      for (int t = 0; t < nt; ++t) s += v[t * tstride];
-      acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, s, acc);
+      double sv = 0.0;
+      for (int t = 0; t < nt; ++t) sv += v[t * tstride];
+      acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, sv, acc);
     }
-    y[S.off + P.coff[k] + moff_h(Lk, m) + i] = acc;
+    y[S.off + P.coff[k] + i] = acc;
   }
 }
 
 // z[sys][coff_k + idx] = sum_k' Dinv[u][k][k'] r[sys][coff_k' + idx'] over active k'
+// (grid: one block per work-list entry over the systems, packed index u of P.Lc)
 __global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ z,
-                             const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs) {
-  const int m = blockIdx.y;
-  const SysDev S = sys[blockIdx.z];
+                             const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
+                             const int4* __restrict__ wl) {
+  const int4 w = wl[blockIdx.x];
+  const SysDev S = sys[w.x];
   const ProbDev P = probs[S.prob];
   const int Lc = P.Lc, nc = P.nc;
-  if (m > Lc) return;
-  const int nsl = Lc - m + 1;
-  const int np = (m == 0) ? 1 : 2;
   const double* rs = r + S.off;
   double* zs = z + S.off;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x) {
-    const int part = i / nsl, ll = i % nsl, l = m + ll;
-    const int64_t u = moff_h(Lc, m) + i;
+  for (int u = w.y + threadIdx.x; u < w.z; u += blockDim.x) {
+    int m, part, ll;
+    unpack_lm(Lc, u, m, part, ll);
+    const int l = m + ll;
     double rv[8];
     for (int k = 0; k < nc; ++k) {
       const int L = P.lk[k];
@@ -140,7 +142,7 @@ __global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ 
       const int L = P.lk[k];
       if (l > L) continue;
       double acc = 0.0;
-      for (int kp = 0; kp < nc; ++kp) acc = fma(P.Dinv[(u * nc + k) * nc + kp], rv[kp], acc);
+      for (int kp = 0; kp < nc; ++kp) acc = fma(P.Dinv[((int64_t)u * nc + k) * nc + kp], rv[kp], acc);
       zs[P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] = acc;
     }
   }
@@ -153,21 +155,22 @@ __device__ __forceinline__ double block_sum256(double acc, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// y[sys][coff_k + idx] = C^-1_{k,l} x[sys][coff_k + idx]
+// y[sys][coff_k + idx] = C^-1_{k,l} x[sys][coff_k + idx] (work list over rows)
 __global__ void k_prior(double* __restrict__ y, const double* __restrict__ x, const SysDev* __restrict__ sys,
-                        const ProbDev* __restrict__ probs, const int2* __restrict__ rows) {
-  const int m = blockIdx.y;
-  const int2 row = rows[blockIdx.z];
+                        const ProbDev* __restrict__ probs, const int2* __restrict__ rows,
+                        const int4* __restrict__ wl) {
+  const int4 w = wl[blockIdx.x];
+  const int2 row = rows[w.x];
   const SysDev S = sys[row.x];
   const ProbDev P = probs[S.prob];
   const int k = row.y;
   const int Lk = P.lk[k];
-  if (m > Lk) return;
-  const int nsl = Lk - m + 1;
-  const int np = (m == 0) ? 1 : 2;
-  const int64_t o = S.off + P.coff[k] + moff_h(Lk, m);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nsl; i += gridDim.x * blockDim.x)
-    y[o + i] = P.dInv[(int64_t)(m + i % nsl) * P.nc + k] * x[o + i];
+  const int64_t o = S.off + P.coff[k];
+  for (int i = w.y + threadIdx.x; i < w.z; i += blockDim.x) {
+    int m, part, ll;
+    unpack_lm(Lk, i, m, part, ll);
+    y[o + i] = P.dInv[(int64_t)(m + ll) * P.nc + k] * x[o + i];
+  }
 }
 
 // One block per (r, nu, k) of a single-problem Exec (see exec_mix_grad).
@@ -353,9 +356,8 @@ inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
               const double* act = nullptr) {
-  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nrows);
-  hipLaunchKernelGGL(k_mix_back, gr, dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.rows.p, dmode, dsqrt,
-                     usep, act);
+  hipLaunchKernelGGL(k_mix_back, dim3(e.nwl_rows), dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.rows.p,
+                     e.wl_rows.p, dmode, dsqrt, usep, act);
   CRS_HIP(hipGetLastError());
 }
 
@@ -485,6 +487,22 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
     for (int k = 0; k < models[e->hsys[sy].prob]->ncomp; ++k) rows.push_back(make_int2(sy, k));
   e->nrows = (int)rows.size();
   e->rows.upload(rows, s);
+  // work lists: contiguous packed-index ranges of kWorkBlock per block
+  std::vector<int4> wlr, wls;
+  for (int r = 0; r < e->nrows; ++r) {
+    const crs_model m = models[e->hsys[rows[r].x].prob];
+    const int64_t n = (int64_t)(m->lk[rows[r].y] + 1) * (m->lk[rows[r].y] + 1);
+    for (int64_t a = 0; a < n; a += kWorkBlock) wlr.push_back(make_int4(r, (int)a, (int)std::min<int64_t>(n, a + kWorkBlock), 0));
+  }
+  for (int sy = 0; sy < e->nsys; ++sy) {
+    const crs_model m = models[e->hsys[sy].prob];
+    const int64_t n = (int64_t)(m->Lc + 1) * (m->Lc + 1);
+    for (int64_t a = 0; a < n; a += kWorkBlock) wls.push_back(make_int4(sy, (int)a, (int)std::min<int64_t>(n, a + kWorkBlock), 0));
+  }
+  e->nwl_rows = (int)wlr.size();
+  e->nwl_sys = (int)wls.size();
+  e->wl_rows.upload(wlr, s);
+  e->wl_sys.upload(wls, s);
   const size_t nn = (size_t)e->ntot;
   e->r.alloc(nn);
   e->z.alloc(nn);
@@ -508,7 +526,7 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip
       skip.mapsys = g.mapsys.p;
       skip.act = act;
     }
-    dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, g.nmaps);
+    dim3 gr((unsigned)((g.nalm + kWorkBlock - 1) / kWorkBlock), g.nmaps);
     hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, in, e.dsys.p, e.dprobs.p, g.slots.p, pinv ? 1 : 0,
                        g.lmax, g.uhat.p, g.nalm, act);
     CRS_HIP(hipGetLastError());
@@ -542,8 +560,7 @@ void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t
 
 void exec_diag(Exec& e, const double* r, double* z, hipStream_t s) {
   CRS_CHECK(e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
-  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nsys);
-  hipLaunchKernelGGL(k_diag_apply, gr, dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p);
+  hipLaunchKernelGGL(k_diag_apply, dim3(e.nwl_sys), dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p, e.wl_sys.p);
   CRS_HIP(hipGetLastError());
 }
 
@@ -580,8 +597,8 @@ void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
 
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s) {
   // the back-mix with no band terms: y = C^-1 x
-  dim3 gr((2 * (e.Lc + 1) + 255) / 256, e.Lc + 1, e.nrows);
-  hipLaunchKernelGGL(k_prior, gr, dim3(256), 0, s, y, x, e.dsys.p, e.dprobs.p, e.rows.p);
+  hipLaunchKernelGGL(k_prior, dim3(e.nwl_rows), dim3(256), 0, s, y, x, e.dsys.p, e.dprobs.p, e.rows.p,
+                     e.wl_rows.p);
   CRS_HIP(hipGetLastError());
 }
 
@@ -599,7 +616,7 @@ void exec_project(Exec& e, const double* x, const std::vector<std::vector<double
   for (auto& g : e.groups) {
     const int64_t npix = g.grid->npix;
     g.pix.alloc((size_t)g.nmaps * npix);
-    dim3 gr((2 * (g.lmax + 1) + 255) / 256, g.lmax + 1, g.nmaps);
+    dim3 gr((unsigned)((g.nalm + kWorkBlock - 1) / kWorkBlock), g.nmaps);
     hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, x, e.dsys.p, e.dprobs.p, g.slots.p, 0, g.lmax, g.uhat.p,
                        g.nalm, (const double*)nullptr);
     CRS_HIP(hipGetLastError());

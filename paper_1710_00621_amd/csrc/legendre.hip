@@ -887,16 +887,16 @@ static int adj_nm(int nmaps, int R) {
 static bool adj_mfma(int nmaps, bool square) { return !square && nmaps >= mfma_min_maps(); }
 
 // 64-pair tiles per wave of the MFMA adjoint: two once that still leaves
-// >= 4096 waves (CRS_LEG_TA fixes it: tuning)
-static int adj_mfma_t(int npairs, int L) {
+// >= 4096 waves over all map groups (CRS_LEG_TA fixes it: tuning)
+static int adj_mfma_t(int npairs, int L, int nmaps) {
   if (const char* e = std::getenv("CRS_LEG_TA")) return std::atoi(e) == 2 ? 2 : 1;
   const long nt = (npairs + 63) / 64;
-  return (long)(L + 1) * ((nt + 1) / 2) >= 4096 ? 2 : 1;
+  return (long)(L + 1) * ((nt + 1) / 2) * ((nmaps + 7) / 8) >= 4096 ? 2 : 1;
 }
 
 int leg_adjoint_tiles(int npairs, int L, int nmaps, bool square) {
   if (adj_mfma(nmaps, square)) {
-    const int t = adj_mfma_t(npairs, L);
+    const int t = adj_mfma_t(npairs, L, nmaps);
     return ((npairs + 63) / 64 + t - 1) / t;
   }
   const int R = adj_r(npairs, L);
@@ -912,7 +912,7 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
     const int nmb = (L + 1 + 3) / 4;
     const int nmb8 = (nmb + 7) / 8 * 8;
     dim3 grid(nmb8 * ntg, (nmaps + 7) / 8);
-    if (adj_mfma_t(a.npairs, L) == 2)
+    if (adj_mfma_t(a.npairs, L, nmaps) == 2)
       hipLaunchKernelGGL(k_leg_adjoint_mfma<2>, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride,
                          tstride, ntg);
     else

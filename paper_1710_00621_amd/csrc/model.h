@@ -17,6 +17,36 @@ __host__ __device__ inline int64_t moff_h(int L, int m) {
 }
 __host__ __device__ inline int64_t tri_h(int L, int m) { return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2; }
 
+// (m, part, l - m) of packed index i (0 <= i < (L+1)^2) in the packed m-major
+// layout: [m = 0: l = 0..L], then for m >= 1 [cos: l = m..L][sin: l = m..L].
+// The m >= 1 blocks up to k hold S(k) = k (2L + 1) - k^2 entries; m - 1 is
+// the largest k with S(k) <= i - (L + 1) (root of the quadratic, then exact
+// integer correction).
+__host__ __device__ inline void unpack_lm(int L, int64_t i, int& m, int& part, int& ll) {
+  if (i <= L) {
+    m = 0;
+    part = 0;
+    ll = (int)i;
+    return;
+  }
+  const int64_t j = i - (L + 1);
+  const int64_t b = 2LL * L + 1;
+  const double bd = (double)b;
+  int64_t k = (int64_t)floor((bd - sqrt(bd * bd - 4.0 * (double)j)) * 0.5);
+  if (k < 0) k = 0;
+  while ((k + 1) * b - (k + 1) * (k + 1) <= j) ++k;
+  while (k > 0 && k * b - k * k > j) --k;
+  m = (int)k + 1;
+  const int64_t w = j - (k * b - k * k);
+  const int nsl = L - m + 1;
+  part = w >= nsl ? 1 : 0;
+  ll = (int)(w - (int64_t)part * nsl);
+}
+
+// Work lists of the packed-index kernels: one entry per block, (row, first,
+// end) of a contiguous range of one row's packed indices.
+constexpr int kWorkBlock = 256;
+
 struct Band {
   crs_grid grid = nullptr;
   int lmax = 0;
@@ -82,6 +112,10 @@ struct Exec {
   DevBuf<SysDev> dsys;
   DevBuf<int2> rows;              // (system, component) rows of the back-mix
   int nrows = 0;
+  DevBuf<int4> wl_rows;           // work list over rows: (row, first, end) per block
+  int nwl_rows = 0;
+  DevBuf<int4> wl_sys;            // work list over systems (component-space index of P.Lc)
+  int nwl_sys = 0;
   std::vector<DevBuf<const double*>> vptr;
   std::vector<DevBuf<int>> binfo;
   bool has_diag = true;
