@@ -168,40 +168,43 @@ __device__ __forceinline__ void syn_acc(SynAcc<NM, R>& A, Grp<R>& G, double gl, 
   }
 }
 
-template <int NM, int R, int NA, bool HAS_S>
-__device__ __forceinline__ void syn_plain(SynAcc<NM, R>& A, Grp<R>& G, cdouble* gb, cdouble* const* ub,
-                                          int nsl, int l, int stop) {
-  constexpr int J0 = R - NA;
+// One chunk of B steps from l (B even, so the even / odd accumulators keep
+// their roles).  EV: some lane may start inside the chunk; every step then
+// checks for start events (wave-uniform test per group, start values and
+// the next event only at an event).
+template <int NM, int R, bool HAS_S, bool EV>
+__device__ __forceinline__ void syn_chunk(SynAcc<NM, R>& A, Grp<R>& G, const LegArgs& a, int m, int base,
+                                          int lane, cdouble* gb, cdouble* const* ub, int nsl, int l) {
   constexpr int B = (NM == 1) ? 8 : ((NM == 2) ? 4 : 2);
-  for (; l + B <= stop; l += B) {
-    l = __builtin_amdgcn_readfirstlane(l);
-    cdouble* gp = gb + l;
-    double gv[B], uc[B][NM], us[B][NM];
+  l = __builtin_amdgcn_readfirstlane(l);
+  cdouble* gp = gb + l;
+  double gv[B], uc[B][NM], us[B][NM];
 #pragma unroll
-    for (int i = 0; i < B; ++i) gv[i] = gp[i];
+  for (int i = 0; i < B; ++i) gv[i] = gp[i];
 #pragma unroll
-    for (int k = 0; k < NM; ++k) {
-      cdouble* up = ub[k] + l;
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        uc[i][k] = up[i];
-        us[i][k] = HAS_S ? up[i + nsl] : 0.0;
-      }
-    }
+  for (int k = 0; k < NM; ++k) {
+    cdouble* up = ub[k] + l;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      syn_acc<NM, R, J0, HAS_S>(A, G, gv[i], uc[i], us[i]);
-      syn_swap<NM, R>(A);
+      uc[i][k] = up[i];
+      us[i][k] = HAS_S ? up[i + nsl] : 0.0;
     }
   }
-  for (; l < stop; ++l) {
-    double uc[NM], us[NM];
 #pragma unroll
-    for (int k = 0; k < NM; ++k) {
-      uc[k] = uld(ub[k], l);
-      us[k] = HAS_S ? uld(ub[k], l + nsl) : 0.0;
+  for (int i = 0; i < B; ++i) {
+    if (EV) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const double c = grp_event_step<R>(G, j, a, m, base, lane, l + i, gv[i]);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+          A.X[j][k][0] = fma(c, uc[i][k], A.X[j][k][0]);
+          if (HAS_S) A.X[j][k][1] = fma(c, us[i][k], A.X[j][k][1]);
+        }
+      }
+    } else {
+      syn_acc<NM, R, 0, HAS_S>(A, G, gv[i], uc[i], us[i]);
     }
-    syn_acc<NM, R, J0, HAS_S>(A, G, uld(gb, l), uc, us);
     syn_swap<NM, R>(A);
   }
 }
@@ -248,21 +251,20 @@ __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, in
 #pragma unroll
     for (int k = 0; k < NM; ++k) A.X[j][k][0] = A.X[j][k][1] = A.Y[j][k][0] = A.Y[j][k][1] = 0.0;
   // all R groups step from the first start of any of them (groups that have
-  // not started carry zero state and add zeros)
+  // not started carry zero state and add zeros), in chunks of B steps; a
+  // chunk takes the event-checked path only if a start falls inside it
+  constexpr int B = (NM == 1) ? 8 : ((NM == 2) ? 4 : 2);
   int l = G.lw[R - 1];
-  while (l <= L) {
+  for (; l + B <= L + 1; l += B) {
     int ne = G.nx[0];
 #pragma unroll
     for (int j = 1; j < R; ++j) ne = min(ne, G.nx[j]);
-    if (ne == l) {
-      syn_event<NM, R, R, HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l);
-      ++l;
-      continue;
-    }
-    const int stop = min(ne, L + 1);
-    syn_plain<NM, R, R, HAS_S>(A, G, gb, ub, nsl, l, stop);
-    l = stop;
+    if (ne >= l + B)
+      syn_chunk<NM, R, HAS_S, false>(A, G, a, m, base, lane, gb, ub, nsl, l);
+    else
+      syn_chunk<NM, R, HAS_S, true>(A, G, a, m, base, lane, gb, ub, nsl, l);
   }
+  for (; l <= L; ++l) syn_event<NM, R, R, HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l);
   // X holds parity (L + 1 - m) & 1 (the loop always ends at l = L + 1, or
   // never ran, in which case X = Y = 0)
   const bool x_is_odd = ((L + 1 - m) & 1) != 0;
@@ -810,10 +812,11 @@ __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
 // Ring-pair groups per lane: larger R amortises the scalar coefficient
 // loads and the adjoint's cross-lane reduction over more pairs, smaller R
 // gives more waves.  Take the largest R (up to rmax) that still leaves
-// `want` waves in the launch.  Measured on MI355X (HEALPix Nside 64..1024):
-// synthesis is fastest at R = 1 throughout, the adjoint at R = 2 once that
-// leaves >= 4096 waves.  The environment variables CRS_LEG_RS and
-// CRS_LEG_RA fix R for synthesis and adjoint (tuning).
+// `want` waves in the launch.  Measured on MI355X (HEALPix Nside 64..1024,
+// one map): synthesis is fastest at R = 2 once that leaves >= 4096 waves
+// (Nside 1024 / L 2000: 0.68 ms vs 0.75 ms at R = 1 and R = 4), the adjoint
+// at R = 4 (0.94 ms vs 1.28 ms at R = 2).  The environment variables
+// CRS_LEG_RS and CRS_LEG_RA fix R for synthesis and adjoint (tuning).
 static int pick_r(int npairs, int L, int rmax, long want, const char* env, int envmax) {
   if (const char* e = std::getenv(env)) {
     const int r = std::atoi(e);
@@ -858,7 +861,7 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
     return;
   }
   const int nm = syn_nm(nmaps);
-  const int R = pick_r(a.npairs, L, std::max(1, 4 / nm), 1L << 40, "CRS_LEG_RS", std::max(1, 4 / nm));
+  const int R = pick_r(a.npairs, L, std::max(1, std::min(2, 4 / nm)), 4096, "CRS_LEG_RS", std::max(1, 4 / nm));
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
