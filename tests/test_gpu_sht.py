@@ -155,3 +155,88 @@ def test_sht_full_size_sampled(nside, lmax):
         if m > 0:
             refs = c * (Hs[:, m] @ lam)
             assert _rel(got_a[o + n:o + 2 * n], refs) < SHT_TOL, m
+
+
+def _sampled_adjoint_ref(og, lmax, maps, ms):
+    """Oracle adjoint coefficients at the sampled m for every map (rows)."""
+    nm = maps.shape[0]
+    Hc = np.zeros((nm, og.nring, len(ms)))
+    Hs = np.zeros((nm, og.nring, len(ms)))
+    for r in range(og.nring):
+        phi = og.ring_phi(r)
+        f = maps[:, og.offset[r]:og.offset[r] + og.nphi[r]]
+        arg = np.outer(phi, ms)
+        Hc[:, r] = f @ np.cos(arg)
+        Hs[:, r] = f @ np.sin(arg)
+    sweep = LegendreSweep(og.z, og.sint, lmax)
+    out = {}
+    for i, m in enumerate(ms):
+        sweep.skip_to(m)
+        lam = sweep.table(m)
+        c = 1.0 if m == 0 else math.sqrt(2.0)
+        out[m] = (c * (Hc[:, :, i] @ lam), c * (Hs[:, :, i] @ lam))
+    return out
+
+
+def test_sht_full_size_sampled_many_maps():
+    """Nside 1024, L = 2000 with 6 maps (the matrix-core kernels at the size
+    and launch configuration of the benchmark): synthesis on sampled rings
+    and the adjoint on sampled m for every map, against the oracle."""
+    torch, crsolve = _setup()
+    nside, lmax, nm = 1024, 2000, 6
+    print(f"case full-size sampled nside={nside} lmax={lmax} nmaps={nm}", flush=True)
+    g = crsolve.Grid.healpix(nside)
+    og = geometry.healpix(nside)
+    rng = np.random.default_rng(12)
+    ell = sht.lm_arrays(lmax)[0]
+    alm = rng.standard_normal((nm, sht.nalm(lmax))) / np.sqrt(1.0 + ell)
+    dev = torch.device("cuda")
+    got = crsolve.sht_synth(g, lmax, torch.tensor(alm, device=dev)).cpu().numpy()
+    rings = [0, 3, nside - 1, 2 * nside - 1, 3 * nside + 5, og.nring - 2]
+    sub = _ring_subset(og, np.array(rings))
+    ref = sht.synth(sub, lmax, alm)
+    gs = np.concatenate([got[:, og.offset[r]:og.offset[r] + og.nphi[r]] for r in rings], axis=1)
+    assert _rel(gs, ref) < SHT_TOL
+    maps = rng.standard_normal((nm, og.npix))
+    got_a = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
+    ms = [0, 1, 5, 700, lmax - 2, lmax]
+    ref_a = _sampled_adjoint_ref(og, lmax, maps, ms)
+    for m in ms:
+        n = lmax - m + 1
+        o = sht.m_offset(lmax, m)
+        assert _rel(got_a[:, o:o + n], ref_a[m][0]) < SHT_TOL, m
+        if m > 0:
+            assert _rel(got_a[:, o + n:o + 2 * n], ref_a[m][1]) < SHT_TOL, m
+
+
+FORCED = [
+    # (environment, nmaps): every kernel variant the launchers choose between,
+    # forced at a size the oracle checks in full (ragged tiles: 80 ring pairs)
+    ({"CRS_LEG_RS": "1", "CRS_LEG_RA": "1"}, 1),
+    ({"CRS_LEG_RS": "2", "CRS_LEG_RA": "2"}, 1),
+    ({"CRS_LEG_RS": "4", "CRS_LEG_RA": "4"}, 1),
+    ({"CRS_LEG_RS": "2", "CRS_LEG_RA": "4"}, 2),
+    ({"CRS_LEG_RA": "2"}, 3),
+    ({"CRS_LEG_TA": "1"}, 9),
+    ({"CRS_LEG_TA": "2"}, 9),
+    ({"CRS_LEG_TA": "2", "CRS_LEG_MFMA_MIN": "1"}, 1),
+]
+
+
+@pytest.mark.parametrize("env,nmaps", FORCED)
+def test_sht_kernel_variants_match_oracle(env, nmaps, monkeypatch):
+    torch, crsolve = _setup()
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    print(f"case variants {env} nmaps={nmaps}", flush=True)
+    spec, lmax = ("healpix", 40), 90
+    g = crsolve.Grid.from_spec(spec)
+    og = geometry.make_grid(spec)
+    rng = np.random.default_rng(21)
+    alm = rng.standard_normal((nmaps, sht.nalm(lmax)))
+    maps = rng.standard_normal((nmaps, og.npix))
+    dev = torch.device("cuda")
+    got_map = crsolve.sht_synth(g, lmax, torch.tensor(alm, device=dev)).cpu().numpy()
+    got_alm = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
+    assert _rel(got_map, sht.synth(og, lmax, alm)) < SHT_TOL
+    assert _rel(got_alm, sht.adjoint(og, lmax, maps)) < SHT_TOL
