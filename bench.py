@@ -316,6 +316,15 @@ def main():
         log(f"batched: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
         mode = (f"batched: one stacked PCG over all {nrhs} problems, each iteration one captured "
                 f"hipGraph")
+        # Legendre kernel variant per (grid, L) group, as picked by the autotuner at batch creation
+        groups = {}
+        for p in probs:
+            for b in p["prob"]["bands"]:
+                key = (b["grid"], b["lmax"])
+                groups[key] = groups.get(key, 0) + 1
+        extra["legendre_autotuned"] = {
+            f"{spec[0]} {spec[1]} L{L} x{n} maps": crsolve.legendre_choice(grids[spec], L, n)
+            for (spec, L), n in sorted(groups.items(), key=lambda kv: kv[0][1])}
     if a.workload == "batched" and not a.no_plain:
         # plain: the same problems one constrained_realization call at a time, no graphs
         torch.cuda.synchronize()

@@ -102,6 +102,26 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
 int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride,
                 double* alm, int64_t alm_stride, crs_stream s);
 
+/*
+ * Legendre kernel autotuning (the recurrence and contraction of Sect. 2.1,
+ * the bulk of every transform).  Both transforms have several kernel
+ * variants per shape: the matrix-core contraction (from a few maps on) or
+ * vector FP64 code, and the number of ring pairs per lane / 64-pair tiles
+ * per wave.  crs_autotune_legendre times every variant for (grid, lmax,
+ * nmaps) on the given stream (setup: allocates scratch, synchronises) and
+ * records the fastest synthesis and adjoint for that shape; every later
+ * transform of that shape in the process (sht_synth, sht_adjoint, and the
+ * operators of models and batches created afterwards) uses it.  Batches
+ * (crs_batch_create) tune each of their groups themselves.  Without tuning
+ * the library uses fixed rules measured on MI355X.
+ * crs_legendre_choice writes the variant in use for a shape to out[5]:
+ * synthesis on matrix cores (0/1), synthesis ring pairs per lane, adjoint on
+ * matrix cores (0/1), adjoint ring pairs per lane, adjoint tiles per wave.
+ * Errors: CRS_EINVAL for a NULL grid / out, lmax < 0 or nmaps < 1.
+ */
+int crs_autotune_legendre(crs_grid g, int lmax, int nmaps, crs_stream s);
+int crs_legendre_choice(crs_grid g, int lmax, int nmaps, int* out);
+
 /* ------------------------------------------------------------------ model
  * One band (sky map) nu of Sect. 2.2: grid, band-limit L_nu, beam b_{nu,l}
  * (host, lmax+1; modes above L_nu are not represented), inverse-noise map

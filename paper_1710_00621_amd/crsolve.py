@@ -118,6 +118,25 @@ def sht_synth(grid, lmax, alm, out=None):
     return out[0] if (sq and out.dim() == 2) else out
 
 
+def autotune_legendre(grid, lmax, nmaps, device=None):
+    """Time every Legendre kernel variant for (grid, lmax, nmaps) and keep the
+    fastest synthesis and adjoint for later transforms of that shape."""
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    check(lib().crs_autotune_legendre(grid._h, int(lmax), int(nmaps), _stream(dev)))
+    return legendre_choice(grid, lmax, nmaps)
+
+
+def legendre_choice(grid, lmax, nmaps):
+    """The Legendre kernel variant in use for a shape: dict with synth_mfma,
+    synth_pairs_per_lane, adjoint_mfma, adjoint_pairs_per_lane,
+    adjoint_tiles_per_wave."""
+    out = (ctypes.c_int * 5)()
+    check(lib().crs_legendre_choice(grid._h, int(lmax), int(nmaps), out))
+    keys = ("synth_mfma", "synth_pairs_per_lane", "adjoint_mfma", "adjoint_pairs_per_lane",
+            "adjoint_tiles_per_wave")
+    return dict(zip(keys, list(out)))
+
+
 def sht_adjoint(grid, lmax, maps, out=None):
     """Y^T maps (adjoint synthesis, Sect. 3.2)."""
     m, sq = _as2d(maps)

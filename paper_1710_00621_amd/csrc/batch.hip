@@ -32,7 +32,7 @@ int crs_batch_create(const crs_model* models, int nprob, crs_stream st, crs_batc
     hipStream_t s = (hipStream_t)st;
     auto b = std::make_unique<crs_batch_s>();
     b->models.assign(models, models + nprob);
-    b->ex = make_exec(b->models, 1, s);
+    b->ex = make_exec(b->models, 1, s, /*autotune=*/true);
     const Exec& e = *b->ex;
     b->b.alloc((size_t)e.ntot);
     b->x.alloc((size_t)e.ntot);

@@ -280,7 +280,7 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
     launch_tile_sum(p.hs.p, nalm, nmaps, alm, alm_stride, 1, 0, w.uhat.p, nalm, s);
     {
       ProfScope ps(FAM_LEG_SYNTH, leg_flops(p, nmaps), s);
-      launch_leg_synth(leg_args(g, p), nmaps, w.uhat.p, nalm, w.phase.p, pst, s);
+      launch_leg_synth(leg_choice(p.npairs, lmax, nmaps), leg_args(g, p), nmaps, w.uhat.p, nalm, w.phase.p, pst, s);
     }
     {
       ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_SYNTH), s);
@@ -303,7 +303,8 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     GridWork& w = *g->work;
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
     const int64_t pst = (int64_t)g->nring * (lmax + 1);
-    const int ntiles = leg_adjoint_tiles(p.npairs, lmax, nmaps, false);
+    const LegChoice lc = leg_choice(p.npairs, lmax, nmaps);
+    const int ntiles = leg_adjoint_tiles(lc, p.npairs, false);
     w.phase.alloc((size_t)nmaps * pst);
     w.vpart.alloc((size_t)ntiles * nmaps * nalm);
     {
@@ -313,10 +314,41 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     }
     {
       ProfScope ps(FAM_LEG_ADJ, leg_flops(p, nmaps), s);
-      launch_leg_adjoint(leg_args(g, p), nmaps, w.phase.p, pst, w.vpart.p, nalm,
+      launch_leg_adjoint(lc, leg_args(g, p), nmaps, w.phase.p, pst, w.vpart.p, nalm,
                          (int64_t)nmaps * nalm, false, s);
     }
     launch_tile_sum(p.hs.p, nalm, nmaps, w.vpart.p, nalm, ntiles, (int64_t)nmaps * nalm, alm, alm_stride, s);
+    return CRS_OK;
+  });
+}
+
+int crs_autotune_legendre(crs_grid g, int lmax, int nmaps, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(lmax >= 0 && nmaps >= 1, CRS_EINVAL, "lmax < 0 or nmaps < 1");
+    hipStream_t s = (hipStream_t)st;
+    ShtPlan& p = get_plan(g, lmax, s);
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
+    const int64_t pst = (int64_t)g->nring * (lmax + 1);
+    DevBuf<double> uhat;
+    DevBuf<double2> phase;
+    uhat.alloc((size_t)nmaps * nalm);
+    phase.alloc((size_t)nmaps * pst);
+    leg_autotune(leg_args(g, p), nmaps, uhat.p, phase.p, s);
+    return CRS_OK;
+  });
+}
+
+int crs_legendre_choice(crs_grid g, int lmax, int nmaps, int* out) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr && out != nullptr, CRS_EINVAL, "grid or out is NULL");
+    CRS_CHECK(lmax >= 0 && nmaps >= 1, CRS_EINVAL, "lmax < 0 or nmaps < 1");
+    const LegChoice c = leg_choice((g->nring + 1) / 2, lmax, nmaps);
+    out[0] = c.syn_mfma;
+    out[1] = c.syn_r;
+    out[2] = c.adj_mfma;
+    out[3] = c.adj_r;
+    out[4] = c.adj_t;
     return CRS_OK;
   });
 }

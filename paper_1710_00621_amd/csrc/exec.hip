@@ -377,7 +377,7 @@ Exec::~Exec() {
   prof_release(prof_iter);
 }
 
-std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s) {
+std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s, bool autotune) {
   CRS_CHECK(!models.empty() && nrhs >= 1, CRS_EINVAL, "no systems");
   auto e = std::make_unique<Exec>();
   e->probs = models;
@@ -423,9 +423,13 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   }
   for (auto& g : e->groups) {
     g.plan = &get_plan(g.grid, g.lmax, s);
-    g.ntiles = leg_adjoint_tiles(g.plan->npairs, g.lmax, g.nmaps, false);
     g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
     g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
+    g.uhat.alloc((size_t)g.nmaps * g.nalm);
+    g.phase.alloc((size_t)g.nmaps * g.pst);
+    g.leg = autotune ? leg_autotune(leg_args(g.grid, *g.plan), g.nmaps, g.uhat.p, g.phase.p, s)
+                     : leg_choice(g.plan->npairs, g.lmax, g.nmaps);
+    g.ntiles = leg_adjoint_tiles(g.leg, g.plan->npairs, false);
     std::vector<const double*> wa, wp, ta;
     for (const SlotDev& sl : g.hslots) {
       const Band& b = models[e->hsys[sl.sys].prob]->bands[sl.band];
@@ -440,8 +444,6 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
     g.wA.upload(wa, s);
     g.wP.upload(wp, s);
     g.tau.upload(ta, s);
-    g.uhat.alloc((size_t)g.nmaps * g.nalm);
-    g.phase.alloc((size_t)g.nmaps * g.pst);
     g.vpart.alloc((size_t)g.ntiles * g.nmaps * g.nalm);
   }
   // per-problem device views
@@ -534,7 +536,7 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip
     la.skip = skip;
     {
       ProfScope ps(FAM_LEG_SYNTH, leg_flops(*g.plan, g.nmaps), s);
-      launch_leg_synth(la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
+      launch_leg_synth(g.leg, la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
     }
     {
       ProfScope ps(FAM_RING, ring_bytes(g.grid, g.lmax, g.nmaps, RING_ROUNDTRIP) + (double)g.nmaps * g.grid->npix * 8.0,
@@ -544,7 +546,8 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip
     }
     {
       ProfScope ps(FAM_LEG_ADJ, leg_flops(*g.plan, g.nmaps), s);
-      launch_leg_adjoint(la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false, s);
+      launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
+                         s);
     }
   }
 }
@@ -581,7 +584,7 @@ void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,
                        g.wptr.p, npix);
     CRS_HIP(hipGetLastError());
     launch_ring(g.grid, g.lmax, RING_ADJOINT, g.nmaps, g.phase.p, g.pst, g.pix.p, nullptr, npix, nullptr, 1, s);
-    launch_leg_adjoint(leg_args(g.grid, *g.plan), g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
+    launch_leg_adjoint(g.leg, leg_args(g.grid, *g.plan), g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm,
                        (int64_t)g.nmaps * g.nalm, false, s);
   }
   // the pointer tables were uploaded from host temporaries: finish before they go
@@ -620,7 +623,7 @@ void exec_project(Exec& e, const double* x, const std::vector<std::vector<double
     hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, x, e.dsys.p, e.dprobs.p, g.slots.p, 0, g.lmax, g.uhat.p,
                        g.nalm, (const double*)nullptr);
     CRS_HIP(hipGetLastError());
-    launch_leg_synth(leg_args(g.grid, *g.plan), g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
+    launch_leg_synth(g.leg, leg_args(g.grid, *g.plan), g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
     launch_ring(g.grid, g.lmax, RING_SYNTH, g.nmaps, g.phase.p, g.pst, nullptr, g.pix.p, npix, nullptr, 1, s);
     for (int i = 0; i < g.nmaps; ++i) {
       const SlotDev& sl = g.hslots[i];

@@ -182,13 +182,30 @@ struct LegArgs {
   int lmax, npairs, nring;
   MapSkip skip;
 };
+// Which Legendre kernels run for a (ring pairs, L, maps) shape: synthesis on
+// the matrix cores or vector FP64 with syn_r ring pairs per lane; adjoint on
+// the matrix cores with adj_t 64-pair tiles per wave or vector FP64 with
+// adj_r pairs per lane.  leg_choice gives the autotuned choice for the shape
+// if one was recorded (leg_autotune), else the measured default rules; the
+// environment variables CRS_LEG_MFMA_MIN, CRS_LEG_RS, CRS_LEG_RA and
+// CRS_LEG_TA override either (tuning and tests).  A caller takes the choice
+// once and passes the same one to leg_adjoint_tiles and the launches.
+struct LegChoice {
+  int syn_mfma = 0, syn_r = 1;
+  int adj_mfma = 0, adj_r = 1, adj_t = 1;
+};
+LegChoice leg_choice(int npairs, int lmax, int nmaps);
+// Times every valid variant of both transforms on the given buffers (their
+// contents are overwritten; vpart is allocated internally) and records the
+// fastest per transform for the shape.  Returns the recorded choice.
+LegChoice leg_autotune(const LegArgs& a, int nmaps, double* uhat, double2* phase, hipStream_t s);
 // phase: [nmaps][nring][L+1] double2 (cos, sin parts)
-void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
+void launch_leg_synth(const LegChoice& c, const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s);
 // Adjoint: writes ntiles partial vectors vpart[tile][map][nalm], ntiles as
-// returned here for the same (nmaps, square) as the launch.
-int leg_adjoint_tiles(int npairs, int lmax, int nmaps, bool square);
-void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
+// returned here for the same choice and square flag as the launch.
+int leg_adjoint_tiles(const LegChoice& c, int npairs, bool square);
+void launch_leg_adjoint(const LegChoice& c, const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s);
 

@@ -19,6 +19,9 @@
 // that lane's start values.
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <cstdlib>
 
@@ -809,49 +812,80 @@ __global__ void k_hat_scale(const double* __restrict__ f, int L, int nmaps,
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-// Ring-pair groups per lane: larger R amortises the scalar coefficient
-// loads and the adjoint's cross-lane reduction over more pairs, smaller R
-// gives more waves.  Take the largest R (up to rmax) that still leaves
-// `want` waves in the launch.  Measured on MI355X (HEALPix Nside 64..1024,
-// one map): synthesis is fastest at R = 2 once that leaves >= 4096 waves
-// (Nside 1024 / L 2000: 0.68 ms vs 0.75 ms at R = 1 and R = 4), the adjoint
-// at R = 4 (0.94 ms vs 1.28 ms at R = 2).  The environment variables
-// CRS_LEG_RS and CRS_LEG_RA fix R for synthesis and adjoint (tuning).
-static int pick_r(int npairs, int L, int rmax, long want, const char* env, int envmax) {
-  if (const char* e = std::getenv(env)) {
-    const int r = std::atoi(e);
-    if (r == 1 || r == 2 || r == 4) return std::min(r, envmax);
-  }
+// Default kernel choice (measured on MI355X, HEALPix Nside 64..1024):
+// matrix-core kernels from 4 maps on; vector ring-pair groups per lane R as
+// large as still leaves >= 4096 waves, up to 2 for synthesis (Nside 1024 /
+// L 2000 / 1 map: 0.68 ms vs 0.75 ms at R = 1 and R = 4) and 4 for the adjoint
+// (0.94 ms vs 1.28 ms at R = 2); two 64-pair tiles per matrix-core adjoint
+// wave under the same wave count rule.
+static int largest_r(int npairs, int L, int rmax, long want) {
   for (int R : {4, 2, 1}) {
     if (R > rmax) continue;
     const long tiles = (npairs + 64L * R - 1) / (64L * R);
-    const long waves = (long)(L + 1) * tiles;
-    if (waves >= want) return R;
+    if ((long)(L + 1) * tiles >= want) return R;
   }
   return 1;
 }
 
+// Maps per wave of the vector synthesis: all of them up to 8, else the
+// group size in {8, 6, 4} that leaves the fewest empty slots.
 static int syn_nm(int nmaps) {
   if (nmaps <= 8) return nmaps;
   int best = 8, waste = 1 << 30;
   for (int c : {8, 6, 4}) {
     const int w = ((nmaps + c - 1) / c) * c - nmaps;
-    if (w < waste) { waste = w; best = c; }
+    if (w < waste) {
+      waste = w;
+      best = c;
+    }
   }
   return best;
 }
 
-// Maps from which the synthesis uses the MFMA kernel (8 maps per wave);
-// CRS_LEG_MFMA_MIN overrides (tuning).
-static int mfma_min_maps() {
-  if (const char* e = std::getenv("CRS_LEG_MFMA_MIN")) return std::max(1, std::atoi(e));
-  return 4;
+static int syn_rmax(int nmaps) { return std::max(1, 4 / syn_nm(nmaps)); }
+
+static LegChoice default_choice(int npairs, int L, int nmaps) {
+  LegChoice c;
+  c.syn_mfma = c.adj_mfma = nmaps >= 4;
+  c.syn_r = largest_r(npairs, L, std::min(2, syn_rmax(nmaps)), 4096);
+  c.adj_r = largest_r(npairs, L, 4, 4096);
+  const long nt = (npairs + 63) / 64;
+  c.adj_t = (long)(L + 1) * ((nt + 1) / 2) * ((nmaps + 7) / 8) >= 4096 ? 2 : 1;
+  return c;
 }
 
-void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
+static int env_int(const char* name) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : 0;
+}
+
+static void apply_env(LegChoice& c, int nmaps) {
+  if (const int v = env_int("CRS_LEG_MFMA_MIN")) c.syn_mfma = c.adj_mfma = nmaps >= std::max(1, v);
+  if (const int v = env_int("CRS_LEG_RS"))
+    if (v == 1 || v == 2 || v == 4) c.syn_r = std::min(v, syn_rmax(nmaps));
+  if (const int v = env_int("CRS_LEG_RA"))
+    if (v == 1 || v == 2 || v == 4) c.adj_r = v;
+  if (const int v = env_int("CRS_LEG_TA")) c.adj_t = v == 2 ? 2 : 1;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, LegChoice> g_tuned;  // (npairs, L, nmaps)
+
+LegChoice leg_choice(int npairs, int L, int nmaps) {
+  LegChoice c;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(npairs, L, nmaps));
+    c = it != g_tuned.end() ? it->second : default_choice(npairs, L, nmaps);
+  }
+  apply_env(c, nmaps);
+  return c;
+}
+
+void launch_leg_synth(const LegChoice& c, const LegArgs& a, int nmaps, const double* uhat, int64_t ustride,
                       double2* phase, int64_t pstride, hipStream_t s) {
   const int L = a.lmax;
-  if (nmaps >= mfma_min_maps()) {
+  if (c.syn_mfma) {
     const int ntiles = (a.npairs + 63) / 64;
     const int nmb = (L + 1 + 3) / 4;
     const int nmb8 = (nmb + 7) / 8 * 8;
@@ -861,7 +895,7 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
     return;
   }
   const int nm = syn_nm(nmaps);
-  const int R = pick_r(a.npairs, L, std::max(1, std::min(2, 4 / nm)), 4096, "CRS_LEG_RS", std::max(1, 4 / nm));
+  const int R = std::min(c.syn_r, syn_rmax(nmaps));
   const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
   const int nmb = (L + 1 + 3) / 4;
   const int nmb8 = (nmb + 7) / 8 * 8;
@@ -876,46 +910,28 @@ void launch_leg_synth(const LegArgs& a, int nmaps, const double* uhat, int64_t u
   throw Error{CRS_EINVAL, "no synthesis kernel variant"};
 }
 
-// The adjoint's ring tile count depends on (npairs, L) only, so that the
-// partial-sum buffers and their consumers do not depend on the map count:
-// R is chosen first and the maps per wave follow (R * NM <= 8).
-static int adj_r(int npairs, int L) { return pick_r(npairs, L, 4, 4096, "CRS_LEG_RA", 4); }
-
+// Vector adjoint: R is chosen first and the maps per wave follow (R * NM <= 8).
 static int adj_nm(int nmaps, int R) {
   const int cap = 8 / R;
   const int nm = nmaps >= 4 ? 4 : (nmaps >= 2 ? 2 : 1);
   return std::min(nm, cap);
 }
 
-static bool adj_mfma(int nmaps, bool square) { return !square && nmaps >= mfma_min_maps(); }
-
-// 64-pair tiles per wave of the MFMA adjoint: two once that still leaves
-// >= 4096 waves over all map groups (CRS_LEG_TA fixes it: tuning)
-static int adj_mfma_t(int npairs, int L, int nmaps) {
-  if (const char* e = std::getenv("CRS_LEG_TA")) return std::atoi(e) == 2 ? 2 : 1;
-  const long nt = (npairs + 63) / 64;
-  return (long)(L + 1) * ((nt + 1) / 2) * ((nmaps + 7) / 8) >= 4096 ? 2 : 1;
+int leg_adjoint_tiles(const LegChoice& c, int npairs, bool square) {
+  if (c.adj_mfma && !square) return ((npairs + 63) / 64 + c.adj_t - 1) / c.adj_t;
+  return (npairs + 64 * c.adj_r - 1) / (64 * c.adj_r);
 }
 
-int leg_adjoint_tiles(int npairs, int L, int nmaps, bool square) {
-  if (adj_mfma(nmaps, square)) {
-    const int t = adj_mfma_t(npairs, L, nmaps);
-    return ((npairs + 63) / 64 + t - 1) / t;
-  }
-  const int R = adj_r(npairs, L);
-  return (npairs + 64 * R - 1) / (64 * R);
-}
-
-void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
+void launch_leg_adjoint(const LegChoice& c, const LegArgs& a, int nmaps, const double2* phase, int64_t pstride,
                         double* vpart, int64_t vstride, int64_t tstride, bool square,
                         hipStream_t s) {
   const int L = a.lmax;
-  if (adj_mfma(nmaps, square)) {
-    const int ntg = leg_adjoint_tiles(a.npairs, L, nmaps, square);
-    const int nmb = (L + 1 + 3) / 4;
-    const int nmb8 = (nmb + 7) / 8 * 8;
+  const int ntg = leg_adjoint_tiles(c, a.npairs, square);
+  const int nmb = (L + 1 + 3) / 4;
+  const int nmb8 = (nmb + 7) / 8 * 8;
+  if (c.adj_mfma && !square) {
     dim3 grid(nmb8 * ntg, (nmaps + 7) / 8);
-    if (adj_mfma_t(a.npairs, L, nmaps) == 2)
+    if (c.adj_t == 2)
       hipLaunchKernelGGL(k_leg_adjoint_mfma<2>, grid, dim3(256), 0, s, a, nmaps, phase, pstride, vpart, vstride,
                          tstride, ntg);
     else
@@ -924,20 +940,17 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
     CRS_HIP(hipGetLastError());
     return;
   }
-  const int R = adj_r(a.npairs, L);
+  const int R = c.adj_r;
   const int nm = adj_nm(nmaps, R);
-  const int ntiles = (a.npairs + 64 * R - 1) / (64 * R);
-  const int nmb = (L + 1 + 3) / 4;
-  const int nmb8 = (nmb + 7) / 8 * 8;
-  dim3 grid(nmb8 * ntiles, (nmaps + nm - 1) / nm);
+  dim3 grid(nmb8 * ntg, (nmaps + nm - 1) / nm);
 #define CRS_ADJ(N, RR)                                                                            \
   if (nm == N && R == RR) {                                                                       \
     if (square)                                                                                   \
       hipLaunchKernelGGL((k_leg_adjoint<N, RR, true>), grid, dim3(256), 0, s, a, nmaps, phase,    \
-                         pstride, vpart, vstride, tstride, ntiles);                               \
+                         pstride, vpart, vstride, tstride, ntg);                                  \
     else                                                                                          \
       hipLaunchKernelGGL((k_leg_adjoint<N, RR, false>), grid, dim3(256), 0, s, a, nmaps, phase,   \
-                         pstride, vpart, vstride, tstride, ntiles);                               \
+                         pstride, vpart, vstride, tstride, ntg);                                  \
     CRS_HIP(hipGetLastError());                                                                   \
     return;                                                                                       \
   }
@@ -946,6 +959,93 @@ void launch_leg_adjoint(const LegArgs& a, int nmaps, const double2* phase, int64
   CRS_ADJ(4, 1) CRS_ADJ(4, 2)
 #undef CRS_ADJ
   throw Error{CRS_EINVAL, "no adjoint kernel variant"};
+}
+
+// ------------------------------------------------------------ autotuner
+// Average time of `reps` launches after one warm-up, with HIP events on s.
+template <class F>
+static float time_launches(F&& launch, int reps, hipStream_t s) {
+  launch();
+  hipEvent_t e0, e1;
+  CRS_HIP(hipEventCreate(&e0));
+  CRS_HIP(hipEventCreate(&e1));
+  CRS_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) launch();
+  CRS_HIP(hipEventRecord(e1, s));
+  CRS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  CRS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+LegChoice leg_autotune(const LegArgs& a0, int nmaps, double* uhat, double2* phase, hipStream_t s) {
+  LegArgs a = a0;
+  a.skip = MapSkip{};
+  const int L = a.lmax;
+  const int64_t nalm = (int64_t)(L + 1) * (L + 1);
+  const int64_t pst = (int64_t)a.nring * (L + 1);
+  const LegChoice base = default_choice(a.npairs, L, nmaps);
+  // the largest tile count of any candidate (one 64-pair tile per wave)
+  DevBuf<double> vpart;
+  vpart.alloc((size_t)((a.npairs + 63) / 64) * nmaps * nalm);
+  CRS_HIP(hipMemsetAsync(uhat, 0, (size_t)nmaps * nalm * sizeof(double), s));
+  CRS_HIP(hipMemsetAsync(phase, 0, (size_t)nmaps * pst * sizeof(double2), s));
+  const int reps = 3;
+  LegChoice best = base;
+  float tbest = 1e30f;
+  auto try_syn = [&](LegChoice c) {
+    const float t = time_launches([&] { launch_leg_synth(c, a, nmaps, uhat, nalm, phase, pst, s); }, reps, s);
+    if (t < tbest) {
+      tbest = t;
+      best.syn_mfma = c.syn_mfma;
+      best.syn_r = c.syn_r;
+    }
+  };
+  for (int r : {1, 2, 4}) {
+    if (r > syn_rmax(nmaps)) continue;
+    LegChoice c = base;
+    c.syn_mfma = 0;
+    c.syn_r = r;
+    try_syn(c);
+  }
+  if (nmaps >= 2) {
+    LegChoice c = base;
+    c.syn_mfma = 1;
+    try_syn(c);
+  }
+  tbest = 1e30f;
+  auto try_adj = [&](LegChoice c) {
+    const float t = time_launches([&] {
+      launch_leg_adjoint(c, a, nmaps, phase, pst, vpart.p, nalm, (int64_t)nmaps * nalm, false, s);
+    }, reps, s);
+    if (t < tbest) {
+      tbest = t;
+      best.adj_mfma = c.adj_mfma;
+      best.adj_r = c.adj_r;
+      best.adj_t = c.adj_t;
+    }
+  };
+  for (int r : {1, 2, 4}) {
+    LegChoice c = base;
+    c.adj_mfma = 0;
+    c.adj_r = r;
+    try_adj(c);
+  }
+  if (nmaps >= 2)
+    for (int t : {1, 2}) {
+      LegChoice c = base;
+      c.adj_mfma = 1;
+      c.adj_t = t;
+      try_adj(c);
+    }
+  CRS_HIP(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(a.npairs, L, nmaps)] = best;
+  }
+  return best;
 }
 
 namespace {

@@ -90,6 +90,7 @@ struct ExecGroup {
   crs_grid grid = nullptr;
   int lmax = 0;
   ShtPlan* plan = nullptr;
+  LegChoice leg;                      // Legendre kernels of this group (fixed at creation)
   int nmaps = 0, ntiles = 1;
   int64_t nalm = 0, pst = 0;
   std::vector<SlotDev> hslots;
@@ -133,7 +134,10 @@ struct Exec {
 
 // models: the problems; nrhs right-hand sides per problem (systems are
 // problem-major).  Allocates all workspaces.
-std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s);
+// autotune: time the Legendre kernel variants of every group once per shape
+// (leg_autotune) instead of taking the default rules.
+std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s,
+                                bool autotune = false);
 
 enum OpKind { OP_A = 0, OP_PI = 1 };
 // skip_done: leave out systems whose PCG has finished (their outputs are then

@@ -203,7 +203,8 @@ void build_diag(crs_model m, hipStream_t s) {
   for (int nu = 0; nu < nb; ++nu) {
     Band& b = m->bands[nu];
     ShtPlan& p = get_plan(b.grid, b.lmax, s);
-    const int ntiles = leg_adjoint_tiles(p.npairs, b.lmax, 1, true);
+    const LegChoice lc = leg_choice(p.npairs, b.lmax, 1);
+    const int ntiles = leg_adjoint_tiles(lc, p.npairs, true);
     const int64_t nalm = (int64_t)(b.lmax + 1) * (b.lmax + 1);
     const int64_t pst = (int64_t)b.grid->nring * (b.lmax + 1);
     DevBuf<double2> ph;
@@ -212,7 +213,7 @@ void build_diag(crs_model m, hipStream_t s) {
     vp.alloc((size_t)ntiles * nalm);
     out.alloc((size_t)nalm);
     launch_ring(b.grid, b.lmax, RING_DIAG, 1, ph.p, pst, b.tau.p, nullptr, b.grid->npix, nullptr, 1, s);
-    launch_leg_adjoint(leg_args(b.grid, p), 1, ph.p, pst, vp.p, nalm, nalm, true, s);
+    launch_leg_adjoint(lc, leg_args(b.grid, p), 1, ph.p, pst, vp.p, nalm, nalm, true, s);
     launch_hat_scale(p.f.p, b.lmax, 1, vp.p, nalm, ntiles, nalm, out.p, nalm, true, s);
     dg[nu].resize(nalm);
     CRS_HIP(hipMemcpyAsync(dg[nu].data(), out.p, nalm * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -51,6 +51,9 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.crs_model_create(None, None, ctypes.byref(h)) == L.CRS_EINVAL
     assert lib.sht_synth(None, 4, 1, None, 25, None, 10, None) == L.CRS_EINVAL
     assert lib.apply_A(None, 1, None, None, None) == L.CRS_EINVAL
+    assert lib.crs_autotune_legendre(None, 8, 1, None) == L.CRS_EINVAL
+    out5 = (ctypes.c_int * 5)()
+    assert lib.crs_legendre_choice(None, 8, 1, out5) == L.CRS_EINVAL
     assert lib.pcg_solve(None, 2, 1, None, None, 1e-8, 10, None, None, None, None) == L.CRS_EINVAL
     buf = ctypes.create_string_buffer(256)
     assert lib.crs_last_error(buf, 256) == L.CRS_EINVAL

@@ -240,3 +240,26 @@ def test_sht_kernel_variants_match_oracle(env, nmaps, monkeypatch):
     got_alm = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
     assert _rel(got_map, sht.synth(og, lmax, alm)) < SHT_TOL
     assert _rel(got_alm, sht.adjoint(og, lmax, maps)) < SHT_TOL
+
+
+def test_autotuned_legendre_matches_oracle():
+    """The autotuner records one of the variants for the shape; transforms of
+    that shape then use it and still match the oracle."""
+    torch, crsolve = _setup()
+    spec, lmax, nmaps = ("healpix", 24), 60, 5
+    print(f"case autotune {spec} lmax={lmax} nmaps={nmaps}", flush=True)
+    g = crsolve.Grid.from_spec(spec)
+    og = geometry.make_grid(spec)
+    c = crsolve.autotune_legendre(g, lmax, nmaps)
+    assert c == crsolve.legendre_choice(g, lmax, nmaps)
+    assert c["synth_mfma"] in (0, 1) and c["adjoint_mfma"] in (0, 1)
+    assert c["synth_pairs_per_lane"] in (1, 2, 4) and c["adjoint_pairs_per_lane"] in (1, 2, 4)
+    assert c["adjoint_tiles_per_wave"] in (1, 2)
+    rng = np.random.default_rng(23)
+    alm = rng.standard_normal((nmaps, sht.nalm(lmax)))
+    maps = rng.standard_normal((nmaps, og.npix))
+    dev = torch.device("cuda")
+    got_map = crsolve.sht_synth(g, lmax, torch.tensor(alm, device=dev)).cpu().numpy()
+    got_alm = crsolve.sht_adjoint(g, lmax, torch.tensor(maps, device=dev)).cpu().numpy()
+    assert _rel(got_map, sht.synth(og, lmax, alm)) < SHT_TOL
+    assert _rel(got_alm, sht.adjoint(og, lmax, maps)) < SHT_TOL
