@@ -112,8 +112,8 @@ struct ShtPlan {
   std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
 };
 
-// Rings are launched in classes by FFT length tier (tier t: FFT length
-// <= 1024 * 4^t, ring_tier_threads(t) threads per block).
+// Rings are launched in classes by FFT length tier (ring_tier_maxfft(t),
+// ring_tier_threads(t) threads per block).
 struct RingClass {
   std::vector<int> rings;
   bool blue = false;  // some ring of the class uses Bluestein's convolution
@@ -122,8 +122,11 @@ struct RingClass {
   int maxn = 1;       // longest ring in the class
   int gcap = 0;       // fold scratch words (rings shorter than the block)
 };
-inline int ring_tier_threads(int tier) { return 256 << tier; }
-inline int ring_tier_maxfft(int tier) { return 1024 << (2 * tier); }
+// tiers: FFT length <= 512 / 1024 / 4096 / 16384 with 128 / 256 / 512 / 1024
+// threads, so that a radix-4 stage of the longest transform of a tier keeps
+// every thread busy
+inline int ring_tier_threads(int tier) { return 128 << tier; }
+inline int ring_tier_maxfft(int tier) { return tier == 0 ? 512 : (1024 << (2 * (tier - 1))); }
 
 // Workspace of the public transforms (sht_synth / sht_adjoint).
 struct GridWork {

@@ -450,9 +450,10 @@ void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase,
     hipLaunchKernelGGL((k_ring<NT, MAXN>), grid, dim3(NT), lds, s, a, md, phase, pstride, map_in,    \
                        map_out, mstride, weights, mpw);                                              \
     break;
-      CRS_RING(0, 256, 1024)
-      CRS_RING(1, 512, 4096)
-      CRS_RING(2, 1024, 8192)
+      CRS_RING(0, 128, 512)
+      CRS_RING(1, 256, 1024)
+      CRS_RING(2, 512, 4096)
+      CRS_RING(3, 1024, 8192)
 #undef CRS_RING
       default: throw Error{CRS_EUNSUPPORTED, "ring FFT length above 8192"};
     }
