@@ -154,12 +154,12 @@ __device__ __forceinline__ void syn_swap(SynAcc<NM, R>& A) {
       }
 }
 
-// one step for groups J0..R-1 into X (no swap)
-template <int NM, int R, int J0, bool HAS_S>
+// one step of every group into X (no swap)
+template <int NM, int R, bool HAS_S>
 __device__ __forceinline__ void syn_acc(SynAcc<NM, R>& A, Grp<R>& G, double gl, const double* uc,
                                         const double* us) {
 #pragma unroll
-  for (int j = J0; j < R; ++j) {
+  for (int j = 0; j < R; ++j) {
     const double c = fma(gl * G.z[j], G.a1[j], -G.a0[j]);
     G.a0[j] = G.a1[j];
     G.a1[j] = c;
@@ -206,16 +206,16 @@ __device__ __forceinline__ void syn_chunk(SynAcc<NM, R>& A, Grp<R>& G, const Leg
         }
       }
     } else {
-      syn_acc<NM, R, 0, HAS_S>(A, G, gv[i], uc[i], us[i]);
+      syn_acc<NM, R, HAS_S>(A, G, gv[i], uc[i], us[i]);
     }
     syn_swap<NM, R>(A);
   }
 }
 
-template <int NM, int R, int NA, bool HAS_S>
-__device__ __forceinline__ void syn_event(SynAcc<NM, R>& A, Grp<R>& G, const LegArgs& a, int m, int base,
-                                          int lane, cdouble* gb, cdouble* const* ub, int nsl, int l) {
-  constexpr int J0 = R - NA;
+// one event-checked step at l (the last steps of a wave, fewer than a chunk)
+template <int NM, int R, bool HAS_S>
+__device__ __forceinline__ void syn_step(SynAcc<NM, R>& A, Grp<R>& G, const LegArgs& a, int m, int base,
+                                         int lane, cdouble* gb, cdouble* const* ub, int nsl, int l) {
   const double gl = uld(gb, l);
   double uc[NM], us[NM];
 #pragma unroll
@@ -224,7 +224,7 @@ __device__ __forceinline__ void syn_event(SynAcc<NM, R>& A, Grp<R>& G, const Leg
     us[k] = HAS_S ? uld(ub[k], l + nsl) : 0.0;
   }
 #pragma unroll
-  for (int j = J0; j < R; ++j) {
+  for (int j = 0; j < R; ++j) {
     const double c = grp_event_step<R>(G, j, a, m, base, lane, l, gl);
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
@@ -267,7 +267,7 @@ __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, in
     else
       syn_chunk<NM, R, HAS_S, true>(A, G, a, m, base, lane, gb, ub, nsl, l);
   }
-  for (; l <= L; ++l) syn_event<NM, R, R, HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l);
+  for (; l <= L; ++l) syn_step<NM, R, HAS_S>(A, G, a, m, base, lane, gb, ub, nsl, l);
   // X holds parity (L + 1 - m) & 1 (the loop always ends at l = L + 1, or
   // never ran, in which case X = Y = 0)
   const bool x_is_odd = ((L + 1 - m) & 1) != 0;
@@ -302,10 +302,7 @@ __device__ __forceinline__ void block_coords(int ntiles, int& mb, int& tile) {
 }
 
 template <int NM, int R>
-#ifndef CRS_LEG_WAVES
-#define CRS_LEG_WAVES 1
-#endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRS_LEG_WAVES))) void k_leg_synth(LegArgs a, int nmaps, const double* __restrict__ uhat,
+__global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const double* __restrict__ uhat,
                                                    int64_t ustride, double2* __restrict__ phase,
                                                    int64_t pstride, int ntiles) {
   int mb, tile;
@@ -615,7 +612,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
 }
 
 template <int NM, int R, bool SQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRS_LEG_WAVES))) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
+__global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                      int64_t pstride, double* __restrict__ vpart,
                                                      int64_t vstride, int64_t tstride, int ntiles) {
   __shared__ double wbuf[4][AdjCfg<NM>::NOUT * 65];
