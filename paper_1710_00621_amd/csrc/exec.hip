@@ -110,8 +110,18 @@ __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ di
       const int64_t nalm = (int64_t)(L + 1) * (L + 1);
       const int64_t tstride = (int64_t)gmaps * nalm;
       const double* v = P.vptr[nu] + (int64_t)map * nalm + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      // tile partials, four loads in flight, summed in tile order
       double sv = 0.0;
-      for (int t = 0; t < nt; ++t) sv += v[t * tstride];
+      int t = 0;
+      for (; t + 4 <= nt; t += 4) {
+        const double v0 = v[t * tstride], v1 = v[(t + 1) * tstride];
+        const double v2 = v[(t + 2) * tstride], v3 = v[(t + 3) * tstride];
+        sv += v0;
+        sv += v1;
+        sv += v2;
+        sv += v3;
+      }
+      for (; t < nt; ++t) sv += v[t * tstride];
       acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, sv, acc);
     }
     y[S.off + P.coff[k] + i] = acc;
@@ -370,6 +380,8 @@ void dot_to(Exec& e, const double* a, const double* b, int op, hipStream_t s) {
 }  // namespace
 
 Exec::~Exec() {
+  if (hscal) (void)hipHostFree(hscal);
+  if (hsel) (void)hipHostFree(hsel);
   if (graph_first) (void)hipGraphExecDestroy(graph_first);
   if (graph_iter) (void)hipGraphExecDestroy(graph_iter);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -514,14 +526,17 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   e->xw.alloc(nn);
   e->partial.alloc((size_t)e->nsys * kDotBlocks);
   e->scal.alloc((size_t)e->nsys * kScal);
+  e->cand.alloc((size_t)e->nsys * kScal);
+  CRS_HIP(hipHostMalloc((void**)&e->hscal, (size_t)e->nsys * kScal * sizeof(double), hipHostMallocDefault));
+  CRS_HIP(hipHostMalloc((void**)&e->hsel, (size_t)e->nsys * sizeof(int), hipHostMallocDefault));
   e->dsel.alloc(e->nsys);
   CRS_HIP(hipStreamSynchronize(s));
   return e;
 }
 
-void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip_done) {
+void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act) {
   const bool pinv = kind == OP_PI;
-  const double* act = skip_done ? e.scal.p + S_ACTIVE : nullptr;
+  const bool skip_done = act != nullptr;
   for (auto& g : e.groups) {
     MapSkip skip;
     if (skip_done) {
@@ -552,9 +567,8 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip
   }
 }
 
-void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done) {
-  exec_bands(e, kind, in, s, skip_done);
-  const double* act = skip_done ? e.scal.p + S_ACTIVE : nullptr;
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act) {
+  exec_bands(e, kind, in, s, act);
   if (kind == OP_PI)
     mix_back(e, out, in, 2, 0, 1, s, act);
   else
@@ -635,9 +649,9 @@ void exec_project(Exec& e, const double* x, const std::vector<std::vector<double
 
 namespace {
 
-void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t s, bool skip_done = false) {
+void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t s, const double* act = nullptr) {
   if (precond == CRS_PRECOND_PINV) {
-    exec_apply(e, OP_PI, r, z, s, skip_done);
+    exec_apply(e, OP_PI, r, z, s, act);
   } else if (precond == CRS_PRECOND_DIAG) {
     exec_diag(e, r, z, s);
   } else {
@@ -649,7 +663,7 @@ void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t
 
 // second half of an iteration: z = M r, rho/beta, p = z + beta p
 void iter_precond(Exec& e, int precond, hipStream_t s) {
-  precond_apply(e, precond, e.r.p, e.z.p, s, true);
+  precond_apply(e, precond, e.r.p, e.z.p, s, e.scal.p + S_ACTIVE);
   dot_to(e, e.r.p, e.z.p, 1, s);
   hipLaunchKernelGGL(k_update_p, vgrid(e.nsys), dim3(256), 0, s, e.p.p, e.z.p, e.dsys.p, e.scal.p);
   CRS_HIP(hipGetLastError());
@@ -657,7 +671,7 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
 
 // first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
 void iter_apply(Exec& e, hipStream_t s) {
-  exec_apply(e, OP_A, e.p.p, e.q.p, s, true);
+  exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE);
   dot_to(e, e.p.p, e.q.p, 0, s);
   hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
                      e.partial.p);
@@ -703,12 +717,16 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   CRS_CHECK(rtol > 0.0 && maxiter >= 0, CRS_EINVAL, "rtol must be > 0 and maxiter >= 0");
   const int ns = e.nsys;
   const size_t bytes = (size_t)e.ntot * sizeof(double);
-  std::vector<double> hs((size_t)ns * kScal, 0.0), bb(ns);
+  // scalars and flags go through pinned host memory (plain DMA transfers)
+  double* const hs = e.hscal;
+  const size_t hsb = (size_t)ns * kScal * sizeof(double);
+  std::vector<double> bb(ns);
+  std::fill(hs, hs + (size_t)ns * kScal, 0.0);
   for (int i = 0; i < ns; ++i) hs[i * kScal + S_ACTIVE] = 1.0;
-  CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
   // |b|^2
   dot_to(e, b, b, 4, s);
-  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
   CRS_HIP(hipStreamSynchronize(s));
   std::vector<int> active(ns, 1), status(ns, 0), it_used(ns, 0), sel(ns, 0);
   for (int i = 0; i < ns; ++i) {
@@ -724,9 +742,9 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   precond_apply(e, precond, e.r.p, e.z.p, s);
   CRS_HIP(hipMemcpyAsync(e.p.p, e.z.p, bytes, hipMemcpyDeviceToDevice, s));
   for (int i = 0; i < ns; ++i) hs[i * kScal + S_ACTIVE] = active[i];
-  CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
   dot_to(e, e.r.p, e.z.p, 3, s);
-  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
   CRS_HIP(hipStreamSynchronize(s));
   for (int i = 0; i < ns; ++i)
     if (active[i] && hs[i * kScal + S_ACTIVE] == 0.0) {
@@ -783,7 +801,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       if (it > 1) iter_precond(e, precond, s);
       iter_apply(e, s);
     }
-    CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
     CRS_HIP(hipStreamSynchronize(s));
     if (use_graph && prof) prof_account(it == 1 ? e.prof_first : e.prof_iter);
     bool cand = false;
@@ -810,11 +828,15 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       }
     }
     if (cand) {
-      // true residual of the candidates: t = b - A x
-      exec_apply(e, OP_A, e.xw.p, e.q.p, s);
+      // true residual of the candidates only: t = b - A x (the operator
+      // skips the other systems; their q and t are not used)
+      std::vector<double> cflag((size_t)ns * kScal, 0.0);  // lives past the sync that ends this block
+      for (int i = 0; i < ns; ++i) cflag[(size_t)i * kScal] = sel[i] ? 1.0 : 0.0;
+      CRS_HIP(hipMemcpyAsync(e.cand.p, cflag.data(), hsb, hipMemcpyHostToDevice, s));
+      exec_apply(e, OP_A, e.xw.p, e.q.p, s, e.cand.p);
       hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
       dot_to(e, e.t.p, e.t.p, 4, s);
-      CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
       CRS_HIP(hipStreamSynchronize(s));
       bool restart = false;
       for (int i = 0; i < ns; ++i) {
@@ -831,9 +853,10 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
         hs[i * kScal + S_ACTIVE] = active[i];
         hs[i * kScal + S_RESTART] = sel[i];
       }
-      CRS_HIP(hipMemcpyAsync(e.scal.p, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
       if (restart) {
-        CRS_HIP(hipMemcpyAsync(e.dsel.p, sel.data(), ns * sizeof(int), hipMemcpyHostToDevice, s));
+        std::copy(sel.begin(), sel.end(), e.hsel);
+        CRS_HIP(hipMemcpyAsync(e.dsel.p, e.hsel, ns * sizeof(int), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.r.p, e.t.p, (const double*)nullptr, e.dsys.p,
                            e.dsel.p);
         CRS_HIP(hipGetLastError());
@@ -847,7 +870,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   exec_apply(e, OP_A, e.xw.p, e.q.p, s);
   hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
   dot_to(e, e.t.p, e.t.p, 4, s);
-  CRS_HIP(hipMemcpyAsync(hs.data(), e.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
   CRS_HIP(hipMemcpyAsync(x, e.xw.p, bytes, hipMemcpyDeviceToDevice, s));
   CRS_HIP(hipStreamSynchronize(s));
   int ret = CRS_OK;

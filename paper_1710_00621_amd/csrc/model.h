@@ -121,8 +121,10 @@ struct Exec {
   std::vector<DevBuf<int>> binfo;
   bool has_diag = true;
   // PCG workspace
-  DevBuf<double> r, z, p, q, t, partial, scal;
+  DevBuf<double> r, z, p, q, t, partial, scal, cand;
   DevBuf<int> dsel;
+  double* hscal = nullptr;        // pinned host copy of the scalars [nsys][8]
+  int* hsel = nullptr;            // pinned host selection flags [nsys]
   DevBuf<double> xw;              // iterate (the graphs reference only Exec buffers)
   // captured iteration graphs (keyed by preconditioner and profiling)
   hipStream_t cap_stream = nullptr;
@@ -140,12 +142,13 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
                                 bool autotune = false);
 
 enum OpKind { OP_A = 0, OP_PI = 1 };
-// skip_done: leave out systems whose PCG has finished (their outputs are then
-// not written); used inside the iteration.
-void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, bool skip_done = false);
+// act: per-system flags at stride 8 (the PCG scalars' active slot, or the
+// candidate flags of a convergence check); systems whose flag is 0 are left
+// out (their outputs are not written).  NULL: every system.
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act = nullptr);
 void exec_diag(Exec& e, const double* r, double* z, hipStream_t s);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
-void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, bool skip_done = false);
+void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
 // the band half of exec_rhs (data / omega_1 terms only)
 void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,
