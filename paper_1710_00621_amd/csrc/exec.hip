@@ -132,8 +132,9 @@ __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ di
 // (grid: one block per work-list entry over the systems, packed index u of P.Lc)
 __global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ z,
                              const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
-                             const int4* __restrict__ wl) {
+                             const int4* __restrict__ wl, const double* __restrict__ act) {
   const int4 w = wl[blockIdx.x];
+  if (act && act[kScal * w.x] == 0.0) return;
   const SysDev S = sys[w.x];
   const ProbDev P = probs[S.prob];
   const int Lc = P.Lc, nc = P.nc;
@@ -235,8 +236,13 @@ __global__ __launch_bounds__(256) void k_dq(const double* __restrict__ va, int s
 
 // partial[sys][blk] = this block's slice of a . b (grid: kDotBlocks x nsys)
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                             const SysDev* __restrict__ sys, double* __restrict__ partial) {
+                                             const SysDev* __restrict__ sys, double* __restrict__ partial,
+                                             const double* __restrict__ act) {
   __shared__ double red[4];
+  if (act && act[kScal * blockIdx.y] == 0.0) {  // finished system: its scalars are not used
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const SysDev S = sys[blockIdx.y];
   const double* pa = a + S.off;
   const double* pb = b + S.off;
@@ -304,6 +310,10 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, doubl
                                                    const SysDev* __restrict__ sys, const double* __restrict__ scal,
                                                    double* __restrict__ partial) {
   __shared__ double red[4];
+  if (scal[blockIdx.y * kScal + S_ACTIVE] == 0.0) {  // finished system: x and r stay, |r|^2 unused
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const SysDev S = sys[blockIdx.y];
   const double al = scal[blockIdx.y * kScal + S_ALPHA];
   double* px = x + S.off;
@@ -371,8 +381,9 @@ void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int
   CRS_HIP(hipGetLastError());
 }
 
-void dot_to(Exec& e, const double* a, const double* b, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, vgrid(e.nsys), dim3(256), 0, s, a, b, e.dsys.p, e.partial.p);
+// act: skip systems whose flag is 0 (inside the iteration); NULL: all systems
+void dot_to(Exec& e, const double* a, const double* b, int op, hipStream_t s, const double* act = nullptr) {
+  hipLaunchKernelGGL(k_dot, vgrid(e.nsys), dim3(256), 0, s, a, b, e.dsys.p, e.partial.p, act);
   hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, op, e.partial.p, kDotBlocks, e.scal.p);
   CRS_HIP(hipGetLastError());
 }
@@ -575,9 +586,9 @@ void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t
     mix_back(e, out, in, 1, 0, 0, s, act);
 }
 
-void exec_diag(Exec& e, const double* r, double* z, hipStream_t s) {
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act) {
   CRS_CHECK(e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
-  hipLaunchKernelGGL(k_diag_apply, dim3(e.nwl_sys), dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p, e.wl_sys.p);
+  hipLaunchKernelGGL(k_diag_apply, dim3(e.nwl_sys), dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p, e.wl_sys.p, act);
   CRS_HIP(hipGetLastError());
 }
 
@@ -653,7 +664,7 @@ void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t
   if (precond == CRS_PRECOND_PINV) {
     exec_apply(e, OP_PI, r, z, s, act);
   } else if (precond == CRS_PRECOND_DIAG) {
-    exec_diag(e, r, z, s);
+    exec_diag(e, r, z, s, act);
   } else {
     hipLaunchKernelGGL(k_sub_sel, vgrid(e.nsys), dim3(256), 0, s, z, r, (const double*)nullptr, e.dsys.p,
                        (const int*)nullptr);
@@ -664,7 +675,7 @@ void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t
 // second half of an iteration: z = M r, rho/beta, p = z + beta p
 void iter_precond(Exec& e, int precond, hipStream_t s) {
   precond_apply(e, precond, e.r.p, e.z.p, s, e.scal.p + S_ACTIVE);
-  dot_to(e, e.r.p, e.z.p, 1, s);
+  dot_to(e, e.r.p, e.z.p, 1, s, e.scal.p + S_ACTIVE);
   hipLaunchKernelGGL(k_update_p, vgrid(e.nsys), dim3(256), 0, s, e.p.p, e.z.p, e.dsys.p, e.scal.p);
   CRS_HIP(hipGetLastError());
 }
@@ -672,7 +683,7 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
 // first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
 void iter_apply(Exec& e, hipStream_t s) {
   exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE);
-  dot_to(e, e.p.p, e.q.p, 0, s);
+  dot_to(e, e.p.p, e.q.p, 0, s, e.scal.p + S_ACTIVE);
   hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
                      e.partial.p);
   hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);

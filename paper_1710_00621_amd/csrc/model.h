@@ -146,7 +146,7 @@ enum OpKind { OP_A = 0, OP_PI = 1 };
 // candidate flags of a convergence check); systems whose flag is 0 are left
 // out (their outputs are not written).  NULL: every system.
 void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act = nullptr);
-void exec_diag(Exec& e, const double* r, double* z, hipStream_t s);
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act = nullptr);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
