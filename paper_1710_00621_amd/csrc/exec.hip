@@ -36,6 +36,13 @@ constexpr int kScal = 8;          // scalars per system
 enum { S_RHO = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_ACTIVE = 4, S_BREAK = 5, S_RESTART = 6, S_TMP = 7 };
 
 // ---------------------------------------------------------------- kernels
+__device__ __forceinline__ double block_sum256(double acc, double* red) {
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // uhat[map][i] = c_m f_lm sum_k coef[l][band][k] x[sys][coff_k + idx_k]
 // (grid: packed-index blocks of kWorkBlock x maps)
 __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict__ sys,
@@ -70,13 +77,20 @@ __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict
 // y[sys][coff_k + idx] = diag term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
 // dmode 0: no diag term; 1: (dsqrt ? C^-1/2 : C^-1) din; 2: Pi_l din.
 // (grid: one block per work-list entry over the (system, component) rows)
-__global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ din,
-                           const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
-                           const int2* __restrict__ rows, const int4* __restrict__ wl, int dmode, int dsqrt,
-                           int usep, const double* __restrict__ act) {
+// wpart (optional): this block's part of din . y at wpart[blockIdx.x]
+__global__ __launch_bounds__(256) void k_mix_back(double* __restrict__ y, const double* __restrict__ din,
+                                                  const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
+                                                  const int2* __restrict__ rows, const int4* __restrict__ wl,
+                                                  int dmode, int dsqrt, int usep, const double* __restrict__ act,
+                                                  double* __restrict__ wpart) {
+  __shared__ double red[4];
   const int4 w = wl[blockIdx.x];
   const int2 row = rows[w.x];
-  if (act && act[kScal * row.x] == 0.0) return;
+  if (act && act[kScal * row.x] == 0.0) {
+    if (wpart && threadIdx.x == 0) wpart[blockIdx.x] = 0.0;
+    return;
+  }
+  double dacc = 0.0;
   const SysDev S = sys[row.x];
   const ProbDev P = probs[S.prob];
   const int k = row.y;
@@ -125,16 +139,28 @@ __global__ void k_mix_back(double* __restrict__ y, const double* __restrict__ di
       acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, sv, acc);
     }
     y[S.off + P.coff[k] + i] = acc;
+    if (wpart) dacc = fma(ds[P.coff[k] + i], acc, dacc);
+  }
+  if (wpart) {
+    const double t = block_sum256(dacc, red);
+    if (threadIdx.x == 0) wpart[blockIdx.x] = t;
   }
 }
 
 // z[sys][coff_k + idx] = sum_k' Dinv[u][k][k'] r[sys][coff_k' + idx'] over active k'
 // (grid: one block per work-list entry over the systems, packed index u of P.Lc)
-__global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ z,
-                             const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
-                             const int4* __restrict__ wl, const double* __restrict__ act) {
+// wpart (optional): this block's part of r . z at wpart[blockIdx.x]
+__global__ __launch_bounds__(256) void k_diag_apply(const double* __restrict__ r, double* __restrict__ z,
+                                                    const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
+                                                    const int4* __restrict__ wl, const double* __restrict__ act,
+                                                    double* __restrict__ wpart) {
+  __shared__ double red[4];
   const int4 w = wl[blockIdx.x];
-  if (act && act[kScal * w.x] == 0.0) return;
+  if (act && act[kScal * w.x] == 0.0) {
+    if (wpart && threadIdx.x == 0) wpart[blockIdx.x] = 0.0;
+    return;
+  }
+  double dacc = 0.0;
   const SysDev S = sys[w.x];
   const ProbDev P = probs[S.prob];
   const int Lc = P.Lc, nc = P.nc;
@@ -155,15 +181,13 @@ __global__ void k_diag_apply(const double* __restrict__ r, double* __restrict__ 
       double acc = 0.0;
       for (int kp = 0; kp < nc; ++kp) acc = fma(P.Dinv[((int64_t)u * nc + k) * nc + kp], rv[kp], acc);
       zs[P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll] = acc;
+      dacc = fma(rv[k], acc, dacc);
     }
   }
-}
-
-__device__ __forceinline__ double block_sum256(double acc, double* red) {
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  if (wpart) {
+    const double t = block_sum256(dacc, red);
+    if (threadIdx.x == 0) wpart[blockIdx.x] = t;
+  }
 }
 
 // y[sys][coff_k + idx] = C^-1_{k,l} x[sys][coff_k + idx] (work list over rows)
@@ -255,21 +279,40 @@ __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const
 
 // op 0: alpha = rho / p.q ; op 1: beta = r.z / rho, rho = r.z ; op 2: rr = sum ;
 // op 3: rho = r.z (start) ; op 4: tmp = sum.   One block per system, fixed-order sum.
-__global__ __launch_bounds__(256) void k_scalar(int op, const double* __restrict__ partial, int nblk,
-                                                double* __restrict__ scal) {
+__device__ void scalar_op(int op, double s, double* st);
+
+// the fixed-order sum of partial[first .. first + n) (one block)
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t first, int n) {
   __shared__ double red[256];
-  const int sy = blockIdx.x;
   double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) v += partial[(int64_t)sy * nblk + i];
+  for (int i = threadIdx.x; i < n; i += 256) v += partial[first + i];
   red[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  const double s = red[0];
-  double* st = scal + sy * kScal;
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scalar(int op, const double* __restrict__ partial, int nblk,
+                                                double* __restrict__ scal) {
+  const int sy = blockIdx.x;
+  const double s = sum_partials(partial, (int64_t)sy * nblk, nblk);
+  if (threadIdx.x == 0) scalar_op(op, s, scal + sy * kScal);
+}
+
+// the same with each system's partials a range (first, count) of one array
+// (the per-block partials of a work-list kernel)
+__global__ __launch_bounds__(256) void k_scalar_ranges(int op, const double* __restrict__ partial,
+                                                       const int2* __restrict__ rng, double* __restrict__ scal) {
+  const int sy = blockIdx.x;
+  const int2 r = rng[sy];
+  const double s = sum_partials(partial, r.x, r.y);
+  if (threadIdx.x == 0) scalar_op(op, s, scal + sy * kScal);
+}
+
+__device__ void scalar_op(int op, double s, double* st) {
   const bool active = st[S_ACTIVE] != 0.0;
   if (op == 0) {
     if (!active) { st[S_ALPHA] = 0.0; return; }
@@ -375,9 +418,9 @@ __global__ void k_pix_rhs(double* __restrict__ f, const double* const* __restric
 inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
-              const double* act = nullptr) {
+              const double* act = nullptr, double* wpart = nullptr) {
   hipLaunchKernelGGL(k_mix_back, dim3(e.nwl_rows), dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.rows.p,
-                     e.wl_rows.p, dmode, dsqrt, usep, act);
+                     e.wl_rows.p, dmode, dsqrt, usep, act, wpart);
   CRS_HIP(hipGetLastError());
 }
 
@@ -528,6 +571,21 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   e->nwl_sys = (int)wls.size();
   e->wl_rows.upload(wlr, s);
   e->wl_sys.upload(wls, s);
+  // per system: its blocks in each work list (contiguous, rows being system-major)
+  std::vector<int2> rr(e->nsys, make_int2(0, 0)), rs(e->nsys, make_int2(0, 0));
+  for (int b = (int)wlr.size() - 1; b >= 0; --b) {
+    int2& q = rr[rows[wlr[b].x].x];
+    q.x = b;
+    ++q.y;
+  }
+  for (int b = (int)wls.size() - 1; b >= 0; --b) {
+    int2& q = rs[wls[b].x];
+    q.x = b;
+    ++q.y;
+  }
+  e->rng_rows.upload(rr, s);
+  e->rng_sys.upload(rs, s);
+  e->wpart.alloc((size_t)std::max(e->nwl_rows, e->nwl_sys));
   const size_t nn = (size_t)e->ntot;
   e->r.alloc(nn);
   e->z.alloc(nn);
@@ -578,17 +636,19 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
   }
 }
 
-void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act) {
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act,
+                double* wpart) {
   exec_bands(e, kind, in, s, act);
   if (kind == OP_PI)
-    mix_back(e, out, in, 2, 0, 1, s, act);
+    mix_back(e, out, in, 2, 0, 1, s, act, wpart);
   else
-    mix_back(e, out, in, 1, 0, 0, s, act);
+    mix_back(e, out, in, 1, 0, 0, s, act, wpart);
 }
 
-void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act) {
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act, double* wpart) {
   CRS_CHECK(e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
-  hipLaunchKernelGGL(k_diag_apply, dim3(e.nwl_sys), dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p, e.wl_sys.p, act);
+  hipLaunchKernelGGL(k_diag_apply, dim3(e.nwl_sys), dim3(256), 0, s, r, z, e.dsys.p, e.dprobs.p, e.wl_sys.p, act,
+                     wpart);
   CRS_HIP(hipGetLastError());
 }
 
@@ -672,18 +732,28 @@ void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t
   }
 }
 
-// second half of an iteration: z = M r, rho/beta, p = z + beta p
+// second half of an iteration: z = M r, rho/beta, p = z + beta p (r . z
+// summed inside the preconditioner's last kernel, per work-list block)
 void iter_precond(Exec& e, int precond, hipStream_t s) {
-  precond_apply(e, precond, e.r.p, e.z.p, s, e.scal.p + S_ACTIVE);
-  dot_to(e, e.r.p, e.z.p, 1, s, e.scal.p + S_ACTIVE);
+  const double* act = e.scal.p + S_ACTIVE;
+  if (precond == CRS_PRECOND_PINV) {
+    exec_apply(e, OP_PI, e.r.p, e.z.p, s, act, e.wpart.p);
+    hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_rows.p, e.scal.p);
+  } else if (precond == CRS_PRECOND_DIAG) {
+    exec_diag(e, e.r.p, e.z.p, s, act, e.wpart.p);
+    hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_sys.p, e.scal.p);
+  } else {
+    precond_apply(e, precond, e.r.p, e.z.p, s, act);
+    dot_to(e, e.r.p, e.z.p, 1, s, act);
+  }
   hipLaunchKernelGGL(k_update_p, vgrid(e.nsys), dim3(256), 0, s, e.p.p, e.z.p, e.dsys.p, e.scal.p);
   CRS_HIP(hipGetLastError());
 }
 
 // first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
 void iter_apply(Exec& e, hipStream_t s) {
-  exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE);
-  dot_to(e, e.p.p, e.q.p, 0, s, e.scal.p + S_ACTIVE);
+  exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE, e.wpart.p);
+  hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 0, e.wpart.p, e.rng_rows.p, e.scal.p);
   hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
                      e.partial.p);
   hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);

@@ -117,6 +117,8 @@ struct Exec {
   int nwl_rows = 0;
   DevBuf<int4> wl_sys;            // work list over systems (component-space index of P.Lc)
   int nwl_sys = 0;
+  DevBuf<int2> rng_rows, rng_sys;  // per system: (first block, block count) in wl_rows / wl_sys
+  DevBuf<double> wpart;           // per work-list block partial dot products
   std::vector<DevBuf<const double*>> vptr;
   std::vector<DevBuf<int>> binfo;
   bool has_diag = true;
@@ -145,8 +147,13 @@ enum OpKind { OP_A = 0, OP_PI = 1 };
 // act: per-system flags at stride 8 (the PCG scalars' active slot, or the
 // candidate flags of a convergence check); systems whose flag is 0 are left
 // out (their outputs are not written).  NULL: every system.
-void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act = nullptr);
-void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act = nullptr);
+// wpart (optional): per block of the back-mix work list, its part of in . out
+// (the system sums are the rng_rows ranges of it).
+void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act = nullptr,
+                double* wpart = nullptr);
+// wpart (optional): per block of the system work list, its part of r . z
+void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act = nullptr,
+               double* wpart = nullptr);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
