@@ -5,6 +5,7 @@
 // sky maps and recommends Gauss-Legendre grids where exact quadrature is
 // wanted (Sect. 2.1, Sect. 2.2 below eq:Q).
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 
@@ -36,10 +37,19 @@ void host_sincospi(double x, double* s, double* c) {
   *c = sign_c * cc;
 }
 
+// Radices of an FFT of length n: the power-of-two part 2^e in as few stages
+// as possible (radix 8, with 2^4 as 4 x 4 and a remaining 2^2 as one radix
+// 4), then the odd prime factors in increasing order.
 std::vector<int> factorize(int n) {
   std::vector<int> f;
-  while (n % 4 == 0) { f.push_back(4); n /= 4; }
-  while (n % 2 == 0) { f.push_back(2); n /= 2; }
+  int e = 0;
+  while (n % 2 == 0) { ++e; n /= 2; }
+  int n8 = e / 3, rest = e % 3;
+  if (rest == 1 && n8 > 0) { --n8; rest = 4; }
+  for (int i = 0; i < n8; ++i) f.push_back(8);
+  if (rest == 4) { f.push_back(4); f.push_back(4); }
+  if (rest == 2) f.push_back(4);
+  if (rest == 1) f.push_back(2);
   for (int p = 3; p * p <= n; p += 2)
     while (n % p == 0) { f.push_back(p); n /= p; }
   if (n > 1) f.push_back(n);
@@ -165,8 +175,9 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     const bool half = (n % 2) == 0;
     const int n0 = half ? n / 2 : n;
     auto f0 = factorize(n0);
+    // radices are 2, 4, 8 and primes, so a prime factor above 7 is one > 8
     bool blue = false;
-    for (int v : f0) blue = blue || v > 7;
+    for (int v : f0) blue = blue || v > 8;
     int nf = n0;
     if (blue) {
       nf = 1;
@@ -203,16 +214,24 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     }
     int tier = 0;
     while (ring_tier_maxfft(tier) < nf) ++tier;
-    auto ci = class_of.find(tier);
+    // classes by (tier, Bluestein, odd radix): a class without odd radices
+    // runs a kernel built for power-of-two FFTs only (fewer registers, more
+    // blocks per CU), and Bluestein's longer buffers do not set the LDS size
+    // of the direct rings
+    bool odd = false;
+    for (int v : ff) odd = odd || (v % 2) != 0;
+    const int key = tier * 4 + (blue ? 2 : 0) + (odd ? 1 : 0);
+    auto ci = class_of.find(key);
     if (ci == class_of.end()) {
-      class_of[tier] = (int)g->ring_classes.size();
+      class_of[key] = (int)g->ring_classes.size();
       g->ring_classes.emplace_back();
       g->ring_classes.back().tier = tier;
-      ci = class_of.find(tier);
+      g->ring_classes.back().blue = blue;
+      g->ring_classes.back().odd = odd;
+      ci = class_of.find(key);
     }
     RingClass& rc = g->ring_classes[ci->second];
     rc.rings.push_back(r);
-    rc.blue = rc.blue || blue;
     rc.xcap = std::max(rc.xcap, std::max(nf, n0));
     rc.maxn = std::max(rc.maxn, n);
     const int nt = ring_tier_threads(tier);
@@ -225,6 +244,27 @@ void grid_finalize(crs_grid g, hipStream_t s) {
   for (auto& rc : g->ring_classes) {
     g->d_ring_class.emplace_back();
     g->d_ring_class.back().upload(rc.rings, s);
+  }
+  // the same rings as one class per tier (for launches with too few maps to
+  // fill the GPU with every class of the tier on its own)
+  std::map<int, RingClass, std::greater<int>> by_tier;
+  for (const auto& rc : g->ring_classes) {
+    RingClass& t = by_tier[rc.tier];
+    t.tier = rc.tier;
+    t.blue = t.blue || rc.blue;
+    t.odd = t.odd || rc.odd;
+    t.xcap = std::max(t.xcap, rc.xcap);
+    t.maxn = std::max(t.maxn, rc.maxn);
+    t.gcap = std::max(t.gcap, rc.gcap);
+    t.rings.insert(t.rings.end(), rc.rings.begin(), rc.rings.end());
+  }
+  g->ring_tiers.clear();
+  g->d_ring_tier.clear();
+  for (auto& kv : by_tier) {
+    std::sort(kv.second.rings.begin(), kv.second.rings.end());
+    g->ring_tiers.push_back(kv.second);
+    g->d_ring_tier.emplace_back();
+    g->d_ring_tier.back().upload(kv.second.rings, s);
   }
   if (any_blue) {
     std::vector<double2> t2(kBlueMax);

@@ -109,24 +109,26 @@ struct ShtPlan {
   DevBuf<double> hs;           // packed alm layout: c_m f_lm (plain <-> hat vectors)
   DevBuf<int> ls;              // [L+1][npairs]: first l evaluated (L+1 = never)
   DevBuf<double2> ms;          // [L+1][npairs]: (mu_{ls-1}, mu_ls)
-  std::vector<int> ls_host_minmax;  // unused placeholder for diagnostics
 };
 
 // Rings are launched in classes by FFT length tier (ring_tier_maxfft(t),
-// ring_tier_threads(t) threads per block).
+// ring_tier_threads(t) threads per block), Bluestein or direct, and whether
+// the FFT has odd radices.
 struct RingClass {
   std::vector<int> rings;
-  bool blue = false;  // some ring of the class uses Bluestein's convolution
+  bool blue = false;  // the rings of the class use Bluestein's convolution
+  bool odd = false;   // their FFT lengths have radices 3, 5 or 7
   int tier = 0;
   int xcap = 1;       // complex LDS words for ring data / convolution
   int maxn = 1;       // longest ring in the class
   int gcap = 0;       // fold scratch words (rings shorter than the block)
 };
-// tiers: FFT length <= 512 / 1024 / 4096 / 16384 with 128 / 256 / 512 / 1024
-// threads, so that a radix-4 stage of the longest transform of a tier keeps
-// every thread busy
+// tiers: FFT length <= 512 / 1024 / 4096 / 8192 with 128 / 256 / 512 / 1024
+// threads (the longest FFT is a Bluestein convolution of kBlueMax words)
 inline int ring_tier_threads(int tier) { return 128 << tier; }
-inline int ring_tier_maxfft(int tier) { return tier == 0 ? 512 : (1024 << (2 * (tier - 1))); }
+inline int ring_tier_maxfft(int tier) {
+  return tier == 0 ? 512 : tier == 1 ? 1024 : tier == 2 ? 4096 : kBlueMax;
+}
 
 // Workspace of the public transforms (sht_synth / sht_adjoint).
 struct GridWork {
@@ -153,8 +155,10 @@ struct crs_grid_s {
   crs::DevBuf<double> d_spair;    // sin(theta) of the north ring of each pair
   crs::DevBuf<double2> d_tw;      // twiddles exp(-2 pi i t / N) per distinct N
   int ring_maxn = 1;
-  std::vector<crs::RingClass> ring_classes;
+  std::vector<crs::RingClass> ring_classes;  // by (tier, Bluestein, odd radix)
   std::vector<crs::DevBuf<int>> d_ring_class;
+  std::vector<crs::RingClass> ring_tiers;    // the same rings, one class per tier
+  std::vector<crs::DevBuf<int>> d_ring_tier;
   std::map<int, std::unique_ptr<crs::ShtPlan>> plans;
   std::unique_ptr<crs::GridWork> work;
   int device = 0;

@@ -22,13 +22,14 @@
 //   adjoint    Z = DFT_H(z), E_k = (Z_k + conj Z_{H-k}) / 2,
 //              O_k = (Z_k - conj Z_{H-k}) / (2i), F^_k = E_k + e^{-2 pi i k / Nphi} O_k.
 // Odd rings run a full complex FFT of length Nphi.  The FFT is a mixed-radix
-// Stockham autosort in LDS (radix 4, 2, 3, 5, 7); a length with a prime
+// Stockham autosort in LDS (radix 8, 4, 2, 3, 5, 7); a length with a prime
 // factor above 7 is computed by Bluestein's chirp-z identity
 // n k = (n^2 + k^2 - (k - n)^2) / 2 as a cyclic convolution of power-of-two
 // length M >= 2n - 1 (filter spectrum precomputed per length on the host).
-// One block per (ring, map); rings are launched in up to three classes by
-// FFT length (<= 1024: 256 threads, <= 4096: 512, <= 8192: 1024); within a
-// class the half-length and Bluestein paths are chosen per ring.
+// One block per (ring, map); rings are launched in classes by FFT length
+// (<= 512: 128 threads, <= 1024: 256, <= 4096: 512, <= 8192: 1024), by
+// Bluestein or direct transform, and by whether the FFT has odd radices;
+// the half-length path is chosen per ring.
 #include "internal.h"
 
 namespace crs {
@@ -89,6 +90,26 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], bool inv) {
     const double2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
+  } else if constexpr (R == 8) {
+    // X_k = E_k + w^k O_k, X_{k+4} = E_k - w^k O_k (E, O: 4-point DFTs of the
+    // even and odd samples; w = exp(-/+ i pi / 4))
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    small_dft<4>(e, inv);
+    small_dft<4>(o, inv);
+    constexpr double h = 0.7071067811865475244008444;  // 1 / sqrt(2)
+    double2 t[4];
+    t[0] = o[0];
+    t[1] = inv ? make_double2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+               : make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+    t[2] = inv ? make_double2(-o[2].y, o[2].x) : make_double2(o[2].y, -o[2].x);
+    t[3] = inv ? make_double2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+               : make_double2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], t[k]);
+      v[k + 4] = csub(e[k], t[k]);
+    }
   } else if constexpr (R == 4) {
     const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
     const double2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
@@ -182,14 +203,16 @@ __device__ void stage(double2* x, int n, int Ns, const TwCtx& C, bool inv) {
 }
 
 // In-place DFT of x[0..n) in LDS: forward exp(-2 pi i jk/n), inverse exp(+).
-// POW2: the length is a power of two (radix 4 and 2 only).
+// POW2: the length is a power of two (radix 8, 4 and 2 only).
 template <int NT, int MAXN, bool POW2>
 __device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, int nfac, const TwCtx& C,
                         bool inv) {
   int Ns = 1;
   for (int st = 0; st < nfac; ++st) {
     const int R = fac[st];
-    if (R == 4) {
+    if (R == 8) {
+      stage<8, NT, MAXN>(x, n, Ns, C, inv);
+    } else if (R == 4) {
       stage<4, NT, MAXN>(x, n, Ns, C, inv);
     } else if (R == 2) {
       stage<2, NT, MAXN>(x, n, Ns, C, inv);
@@ -268,7 +291,9 @@ __device__ __forceinline__ double2 fold(const double2* __restrict__ ph, int k, i
   return make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
 }
 
-template <int NT, int MAXN>
+// ODD: the class has FFT lengths with radices 3, 5 or 7 (without it only the
+// power-of-two stages are compiled, which takes far fewer registers).
+template <int NT, int MAXN, bool ODD>
 __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __restrict__ phase,
                                              int64_t pstride, const double* __restrict__ map_in,
                                              double* __restrict__ map_out, int64_t mstride,
@@ -353,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
     if (blue)
       dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, true);
     else
-      fft_lds<NT, MAXN, false>(x, n0, fac, nfac, fc, true);
+      fft_lds<NT, MAXN, !ODD>(x, n0, fac, nfac, fc, true);
     if (mode == RING_SYNTH) {
       double* out = map_out + (int64_t)map * mstride + off;
       if (half) {
@@ -382,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   if (blue)
     dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, false);
   else
-    fft_lds<NT, MAXN, false>(x, n0, fac, nfac, fc, false);
+    fft_lds<NT, MAXN, !ODD>(x, n0, fac, nfac, fc, false);
 
   // forward DFT of the real ring data at bin k (0 <= k < N)
   auto spec = [&](int k) -> double2 {
@@ -432,32 +457,52 @@ void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase,
   base.skip = skip;
   const int mpw = maps_per_weight < 1 ? 1 : maps_per_weight;
   const int md = (int)mode;
-  for (size_t c = 0; c < g->ring_classes.size(); ++c) {
-    const RingClass& rc = g->ring_classes[c];
-    if (rc.rings.empty()) continue;
+  auto launch_class = [&](const RingClass& rc, const int* rings) {
+    if (rc.rings.empty()) return;
     RingArgs a = base;
     a.maxn = rc.maxn;
     a.xcap = rc.xcap;
-    a.rings = g->d_ring_class[c].p;
+    a.rings = rings;
     const dim3 grid((unsigned)rc.rings.size(), nmaps);
     const size_t words = (size_t)rc.xcap + 64 + (2 * rc.maxn + 63) / 64 +
                          (rc.blue ? 64 + kBlueMax / 64 : 0) + rc.gcap;
     a.any_blue = rc.blue ? 1 : 0;
     const size_t lds = words * sizeof(double2);
-    switch (rc.tier) {
-#define CRS_RING(T, NT, MAXN)                                                                          \
-  case T:                                                                                            \
-    hipLaunchKernelGGL((k_ring<NT, MAXN>), grid, dim3(NT), lds, s, a, md, phase, pstride, map_in,    \
-                       map_out, mstride, weights, mpw);                                              \
+    switch (rc.tier * 2 + (rc.odd ? 1 : 0)) {
+#define CRS_RING(T, NT, MAXN, ODD)                                                                   \
+  case T * 2 + ODD:                                                                                  \
+    hipLaunchKernelGGL((k_ring<NT, MAXN, ODD>), grid, dim3(NT), lds, s, a, md, phase, pstride,       \
+                       map_in, map_out, mstride, weights, mpw);                                      \
     break;
-      CRS_RING(0, 128, 512)
-      CRS_RING(1, 256, 1024)
-      CRS_RING(2, 512, 4096)
-      CRS_RING(3, 1024, 8192)
+      CRS_RING(0, 128, 512, false)
+      CRS_RING(0, 128, 512, true)
+      CRS_RING(1, 256, 1024, false)
+      CRS_RING(1, 256, 1024, true)
+      CRS_RING(2, 512, 4096, false)
+      CRS_RING(2, 512, 4096, true)
+      CRS_RING(3, 1024, 8192, false)
+      CRS_RING(3, 1024, 8192, true)
 #undef CRS_RING
       default: throw Error{CRS_EUNSUPPORTED, "ring FFT length above 8192"};
     }
     CRS_HIP(hipGetLastError());
+  };
+  // A tier runs as its separate classes when each of them has enough blocks
+  // to fill the GPU; otherwise as one launch (launches on a stream run one
+  // after another, and a class of a few hundred blocks would leave most CUs
+  // idle for a whole block's duration).
+  constexpr int64_t kMinClassBlocks = 1024;
+  for (size_t t = 0; t < g->ring_tiers.size(); ++t) {
+    const int tier = g->ring_tiers[t].tier;
+    bool split = true;
+    for (const RingClass& rc : g->ring_classes)
+      if (rc.tier == tier) split = split && (int64_t)rc.rings.size() * nmaps >= kMinClassBlocks;
+    if (!split) {
+      launch_class(g->ring_tiers[t], g->d_ring_tier[t].p);
+      continue;
+    }
+    for (size_t c = 0; c < g->ring_classes.size(); ++c)
+      if (g->ring_classes[c].tier == tier) launch_class(g->ring_classes[c], g->d_ring_class[c].p);
   }
 }
 
