@@ -62,6 +62,16 @@ __device__ __forceinline__ double add_xor32(double v) {
   const double y = __longlong_as_double((long long)(((uint64_t)b[1] << 32) | a[1]));
   return x + y;
 }
+// Transposing form: lanes t < 32 get A(t) + A(t + 32), lanes t >= 32 get
+// B(t - 32) + B(t) (both lanes of a pair add in the same order).
+__device__ __forceinline__ double fold32(double A, double B) {
+  const uint64_t ua = __double_as_longlong(A), ub = __double_as_longlong(B);
+  const auto a = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((uint64_t)b[0] << 32) | a[0]));
+  const double y = __longlong_as_double((long long)(((uint64_t)b[1] << 32) | a[1]));
+  return x + y;
+}
 __device__ __forceinline__ double add_xor16(double v) {
   const uint64_t u = __double_as_longlong(v);
   const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
@@ -463,6 +473,7 @@ __global__ __launch_bounds__(256) void k_leg_synth_mfma(LegArgs a, int nmaps, co
 // P[s]; each chunk of CH steps is reduced over the wave's 64 lanes through a
 // wave-private LDS block (no block barrier) in a fixed order and written as
 // the wave's partial v^ (one partial per ring tile of 64 R pairs).
+constexpr int kRedStride = 33;  // row stride (doubles) of the reduction block
 template <int NM>
 struct AdjCfg {
   static constexpr int CH = (8 / NM) < 1 ? 1 : (8 / NM);
@@ -586,19 +597,24 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
         for (int k = 0; k < NM; ++k) P[s][k][0] = P[s][k][1] = 0.0;
       adj_chunk<NM, R, false, SQ, HAS_S>(G, E, O, gv, a, m, base, lane, lc, L, P);
     }
-    // wave-private reduction: wb is [NOUT][65]
+    // wave-private reduction of the 16 outputs u = (s NM + k) 2 + cs.  A
+    // lane-swap step first sums lanes t and t + 32 (outputs u < 8 stay in the
+    // lower half, u + 8 in the upper), so the LDS block wb[16][kRedStride]
+    // holds 32 partials per output; four lanes then sum 8 columns each (the
+    // column groups of lanes t and t ^ 16 are 16 apart: no bank conflicts)
+    // and two more swap steps finish.
 #pragma unroll
-    for (int s = 0; s < CH; ++s)
-#pragma unroll
-      for (int k = 0; k < NM; ++k) {
-        wb[((s * NM + k) * 2 + 0) * 65 + lane] = P[s][k][0];
-        wb[((s * NM + k) * 2 + 1) * 65 + lane] = P[s][k][1];
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int v = u + 8;
+      const double h = fold32(P[u / (NM * 2)][(u >> 1) % NM][u & 1], P[v / (NM * 2)][(v >> 1) % NM][v & 1]);
+      wb[(u + 8 * (lane >> 5)) * kRedStride + (lane & 31)] = h;
+    }
     __builtin_amdgcn_wave_barrier();
     const int o = lane & 15, sub = lane >> 4;
-    double acc = 0.0;
+    const double* wr = wb + o * kRedStride + 8 * (((sub & 1) << 1) | (sub >> 1));
+    double acc = wr[0];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc += wb[o * 65 + sub + 4 * i];
+    for (int i = 1; i < 8; ++i) acc += wr[i];
     acc = add_xor16(acc);
     acc = add_xor32(acc);
     __builtin_amdgcn_wave_barrier();
@@ -615,7 +631,7 @@ template <int NM, int R, bool SQ>
 __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const double2* __restrict__ phase,
                                                      int64_t pstride, double* __restrict__ vpart,
                                                      int64_t vstride, int64_t tstride, int ntiles) {
-  __shared__ double wbuf[4][AdjCfg<NM>::NOUT * 65];
+  __shared__ double wbuf[4][AdjCfg<NM>::NOUT * kRedStride];
   int mb, tile;
   block_coords(ntiles, mb, tile);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
