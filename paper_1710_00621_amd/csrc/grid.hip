@@ -5,7 +5,6 @@
 // sky maps and recommends Gauss-Legendre grids where exact quadrature is
 // wanted (Sect. 2.1, Sect. 2.2 below eq:Q).
 #include <algorithm>
-#include <functional>
 #include <cmath>
 #include <cstring>
 
@@ -245,26 +244,41 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     g->d_ring_class.emplace_back();
     g->d_ring_class.back().upload(rc.rings, s);
   }
-  // the same rings as one class per tier (for launches with too few maps to
-  // fill the GPU with every class of the tier on its own)
-  std::map<int, RingClass, std::greater<int>> by_tier;
-  for (const auto& rc : g->ring_classes) {
-    RingClass& t = by_tier[rc.tier];
-    t.tier = rc.tier;
-    t.blue = t.blue || rc.blue;
-    t.odd = t.odd || rc.odd;
-    t.xcap = std::max(t.xcap, rc.xcap);
-    t.maxn = std::max(t.maxn, rc.maxn);
-    t.gcap = std::max(t.gcap, rc.gcap);
-    t.rings.insert(t.rings.end(), rc.rings.begin(), rc.rings.end());
-  }
-  g->ring_tiers.clear();
-  g->d_ring_tier.clear();
-  for (auto& kv : by_tier) {
-    std::sort(kv.second.rings.begin(), kv.second.rings.end());
-    g->ring_tiers.push_back(kv.second);
-    g->d_ring_tier.emplace_back();
-    g->d_ring_tier.back().upload(kv.second.rings, s);
+  // Launches with few maps merge the classes that would have too few blocks
+  // to fill the GPU on their own into one launch (run by the kernel of their
+  // largest tier).  Which classes are small depends on the map count, but
+  // they are always the first ones in order of ring count, so the merged
+  // class of every such prefix is prepared here.
+  const int ncls = (int)g->ring_classes.size();
+  CRS_CHECK(ncls <= kMaxRingClasses, CRS_EUNSUPPORTED, "too many ring classes");
+  g->ring_small_order.resize(ncls);
+  for (int c = 0; c < ncls; ++c) g->ring_small_order[c] = c;
+  std::stable_sort(g->ring_small_order.begin(), g->ring_small_order.end(), [&](int x, int y) {
+    return g->ring_classes[x].rings.size() < g->ring_classes[y].rings.size();
+  });
+  g->ring_prefix.clear();
+  g->d_ring_prefix.clear();
+  RingClass acc;
+  for (int k = 0; k < ncls; ++k) {
+    const RingClass& rc = g->ring_classes[g->ring_small_order[k]];
+    acc.tier = std::max(acc.tier, rc.tier);
+    acc.blue = acc.blue || rc.blue;
+    acc.odd = acc.odd || rc.odd;
+    acc.xcap = std::max(acc.xcap, rc.xcap);
+    acc.maxn = std::max(acc.maxn, rc.maxn);
+    acc.rings.insert(acc.rings.end(), rc.rings.begin(), rc.rings.end());
+    RingClass m = acc;
+    std::sort(m.rings.begin(), m.rings.end());
+    // fold scratch for the merged kernel's block size
+    const int nt = ring_tier_threads(m.tier);
+    m.gcap = 0;
+    for (int r : m.rings) {
+      const int n = g->nphi[r];
+      if (n <= nt) m.gcap = std::max(m.gcap, n + n * (nt / n));
+    }
+    g->ring_prefix.push_back(m);
+    g->d_ring_prefix.emplace_back();
+    g->d_ring_prefix.back().upload(m.rings, s);
   }
   if (any_blue) {
     std::vector<double2> t2(kBlueMax);

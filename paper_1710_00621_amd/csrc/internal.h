@@ -125,6 +125,7 @@ struct RingClass {
 };
 // tiers: FFT length <= 512 / 1024 / 4096 / 8192 with 128 / 256 / 512 / 1024
 // threads (the longest FFT is a Bluestein convolution of kBlueMax words)
+constexpr int kMaxRingClasses = 16;  // 4 tiers x (Bluestein, odd radix)
 inline int ring_tier_threads(int tier) { return 128 << tier; }
 inline int ring_tier_maxfft(int tier) {
   return tier == 0 ? 512 : tier == 1 ? 1024 : tier == 2 ? 4096 : kBlueMax;
@@ -157,8 +158,9 @@ struct crs_grid_s {
   int ring_maxn = 1;
   std::vector<crs::RingClass> ring_classes;  // by (tier, Bluestein, odd radix)
   std::vector<crs::DevBuf<int>> d_ring_class;
-  std::vector<crs::RingClass> ring_tiers;    // the same rings, one class per tier
-  std::vector<crs::DevBuf<int>> d_ring_tier;
+  std::vector<int> ring_small_order;         // classes by ring count, ascending
+  std::vector<crs::RingClass> ring_prefix;   // [k]: the first k + 1 of them merged
+  std::vector<crs::DevBuf<int>> d_ring_prefix;
   std::map<int, std::unique_ptr<crs::ShtPlan>> plans;
   std::unique_ptr<crs::GridWork> work;
   int device = 0;

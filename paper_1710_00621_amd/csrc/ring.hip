@@ -487,23 +487,21 @@ void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase,
     }
     CRS_HIP(hipGetLastError());
   };
-  // A tier runs as its separate classes when each of them has enough blocks
-  // to fill the GPU; otherwise as one launch (launches on a stream run one
-  // after another, and a class of a few hundred blocks would leave most CUs
-  // idle for a whole block's duration).
+  // Launches on a stream run one after another, so a class of a few hundred
+  // blocks would leave most CUs idle for a whole block's duration: the
+  // classes with fewer than kMinClassBlocks blocks (the first `nsmall` in
+  // order of ring count) run together as one launch, the others on their own.
   constexpr int64_t kMinClassBlocks = 1024;
-  for (size_t t = 0; t < g->ring_tiers.size(); ++t) {
-    const int tier = g->ring_tiers[t].tier;
-    bool split = true;
-    for (const RingClass& rc : g->ring_classes)
-      if (rc.tier == tier) split = split && (int64_t)rc.rings.size() * nmaps >= kMinClassBlocks;
-    if (!split) {
-      launch_class(g->ring_tiers[t], g->d_ring_tier[t].p);
-      continue;
-    }
-    for (size_t c = 0; c < g->ring_classes.size(); ++c)
-      if (g->ring_classes[c].tier == tier) launch_class(g->ring_classes[c], g->d_ring_class[c].p);
-  }
+  const int ncls = (int)g->ring_classes.size();
+  int nsmall = 0;
+  while (nsmall < ncls &&
+         (int64_t)g->ring_classes[g->ring_small_order[nsmall]].rings.size() * nmaps < kMinClassBlocks)
+    ++nsmall;
+  bool small[kMaxRingClasses] = {};
+  for (int k = 0; k < nsmall; ++k) small[g->ring_small_order[k]] = true;
+  for (int c = 0; c < ncls; ++c)
+    if (!small[c]) launch_class(g->ring_classes[c], g->d_ring_class[c].p);
+  if (nsmall > 0) launch_class(g->ring_prefix[nsmall - 1], g->d_ring_prefix[nsmall - 1].p);
 }
 
 }  // namespace crs
