@@ -76,42 +76,56 @@ __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict
 
 // y[sys][coff_k + idx] = diag term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
 // dmode 0: no diag term; 1: (dsqrt ? C^-1/2 : C^-1) din; 2: Pi_l din.
-// (grid: one block per work-list entry over the (system, component) rows)
+// (grid: one block per work-list entry over the systems, packed index u of
+// P.Lc; each thread forms all components of its (l, m), so the band partials
+// of an index are read once, not once per component)
 // wpart (optional): this block's part of din . y at wpart[blockIdx.x]
 __global__ __launch_bounds__(256) void k_mix_back(double* __restrict__ y, const double* __restrict__ din,
                                                   const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
-                                                  const int2* __restrict__ rows, const int4* __restrict__ wl,
-                                                  int dmode, int dsqrt, int usep, const double* __restrict__ act,
-                                                  double* __restrict__ wpart) {
+                                                  const int4* __restrict__ wl, int dmode, int dsqrt, int usep,
+                                                  const double* __restrict__ act, double* __restrict__ wpart) {
   __shared__ double red[4];
   const int4 w = wl[blockIdx.x];
-  const int2 row = rows[w.x];
-  if (act && act[kScal * row.x] == 0.0) {
+  if (act && act[kScal * w.x] == 0.0) {
     if (wpart && threadIdx.x == 0) wpart[blockIdx.x] = 0.0;
     return;
   }
   double dacc = 0.0;
-  const SysDev S = sys[row.x];
+  const SysDev S = sys[w.x];
   const ProbDev P = probs[S.prob];
-  const int k = row.y;
-  const int Lk = P.lk[k];
-  const int nc = P.nc;
+  const int Lc = P.Lc, nc = P.nc;
   const double* __restrict__ coef = usep ? P.cP : P.cA;
   const double* __restrict__ ds = din ? din + S.off : nullptr;
-  for (int i = w.y + threadIdx.x; i < w.z; i += blockDim.x) {
+  for (int u = w.y + threadIdx.x; u < w.z; u += blockDim.x) {
     int m, part, ll;
-    unpack_lm(Lk, i, m, part, ll);
+    unpack_lm(Lc, u, m, part, ll);
     const int l = m + ll;
-    double acc = 0.0;
+    // index of (l, m, part) in each component's layout (-1: above its band-limit)
+    int64_t ix[8];
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ix[k] = -1;
+      acc[k] = 0.0;
+      if (k < nc) {
+        const int L = P.lk[k];
+        if (l <= L) ix[k] = P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      }
+    }
     if (dmode == 1) {
       const double* dt = dsqrt ? P.dSqrt : P.dInv;
-      acc = dt[(int64_t)l * nc + k] * ds[P.coff[k] + i];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < nc && ix[k] >= 0) acc[k] = dt[(int64_t)l * nc + k] * ds[ix[k]];
     } else if (dmode == 2) {
-      for (int kp = 0; kp < nc; ++kp) {
-        const int Lp = P.lk[kp];
-        if (l > Lp) continue;
-        acc = fma(P.dPi[((int64_t)l * nc + k) * nc + kp],
-                  ds[P.coff[kp] + moff_h(Lp, m) + (int64_t)part * (Lp - m + 1) + ll], acc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k >= nc || ix[k] < 0) continue;
+        double a = 0.0;
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp)
+          if (kp < nc && ix[kp] >= 0) a = fma(P.dPi[((int64_t)l * nc + k) * nc + kp], ds[ix[kp]], a);
+        acc[k] = a;
       }
     }
     const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
@@ -136,10 +150,17 @@ __global__ __launch_bounds__(256) void k_mix_back(double* __restrict__ y, const 
         sv += v3;
       }
       for (; t < nt; ++t) sv += v[t * tstride];
-      acc = fma(coef[((int64_t)l * P.nb + nu) * nc + k] * fs, sv, acc);
+      const double* cn = coef + ((int64_t)l * P.nb + nu) * nc;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < nc && ix[k] >= 0) acc[k] = fma(cn[k] * fs, sv, acc[k]);
     }
-    y[S.off + P.coff[k] + i] = acc;
-    if (wpart) dacc = fma(ds[P.coff[k] + i], acc, dacc);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k >= nc || ix[k] < 0) continue;
+      y[S.off + ix[k]] = acc[k];
+      if (wpart) dacc = fma(ds[ix[k]], acc[k], dacc);
+    }
   }
   if (wpart) {
     const double t = block_sum256(dacc, red);
@@ -419,8 +440,8 @@ inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
               const double* act = nullptr, double* wpart = nullptr) {
-  hipLaunchKernelGGL(k_mix_back, dim3(e.nwl_rows), dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.rows.p,
-                     e.wl_rows.p, dmode, dsqrt, usep, act, wpart);
+  hipLaunchKernelGGL(k_mix_back, dim3(e.nwl_sys), dim3(256), 0, s, out, din, e.dsys.p, e.dprobs.p, e.wl_sys.p,
+                     dmode, dsqrt, usep, act, wpart);
   CRS_HIP(hipGetLastError());
 }
 
@@ -571,21 +592,15 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   e->nwl_sys = (int)wls.size();
   e->wl_rows.upload(wlr, s);
   e->wl_sys.upload(wls, s);
-  // per system: its blocks in each work list (contiguous, rows being system-major)
-  std::vector<int2> rr(e->nsys, make_int2(0, 0)), rs(e->nsys, make_int2(0, 0));
-  for (int b = (int)wlr.size() - 1; b >= 0; --b) {
-    int2& q = rr[rows[wlr[b].x].x];
-    q.x = b;
-    ++q.y;
-  }
+  // per system: its blocks in the system work list (contiguous)
+  std::vector<int2> rs(e->nsys, make_int2(0, 0));
   for (int b = (int)wls.size() - 1; b >= 0; --b) {
     int2& q = rs[wls[b].x];
     q.x = b;
     ++q.y;
   }
-  e->rng_rows.upload(rr, s);
   e->rng_sys.upload(rs, s);
-  e->wpart.alloc((size_t)std::max(e->nwl_rows, e->nwl_sys));
+  e->wpart.alloc((size_t)e->nwl_sys);
   const size_t nn = (size_t)e->ntot;
   e->r.alloc(nn);
   e->z.alloc(nn);
@@ -738,7 +753,7 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
   const double* act = e.scal.p + S_ACTIVE;
   if (precond == CRS_PRECOND_PINV) {
     exec_apply(e, OP_PI, e.r.p, e.z.p, s, act, e.wpart.p);
-    hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_rows.p, e.scal.p);
+    hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_sys.p, e.scal.p);
   } else if (precond == CRS_PRECOND_DIAG) {
     exec_diag(e, e.r.p, e.z.p, s, act, e.wpart.p);
     hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_sys.p, e.scal.p);
@@ -753,7 +768,7 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
 // first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
 void iter_apply(Exec& e, hipStream_t s) {
   exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE, e.wpart.p);
-  hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 0, e.wpart.p, e.rng_rows.p, e.scal.p);
+  hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 0, e.wpart.p, e.rng_sys.p, e.scal.p);
   hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
                      e.partial.p);
   hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);

@@ -213,24 +213,26 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     }
     int tier = 0;
     while (ring_tier_maxfft(tier) < nf) ++tier;
-    // classes by (tier, Bluestein, odd radix): a class without odd radices
-    // runs a kernel built for power-of-two FFTs only (fewer registers, more
-    // blocks per CU), and Bluestein's longer buffers do not set the LDS size
-    // of the direct rings
+    // classes by (tier, Bluestein, odd radix) from the 512-thread tier up: a
+    // class without odd radices runs a kernel built for power-of-two FFTs
+    // only (72 instead of 115 registers: more blocks per CU), and Bluestein's
+    // longer buffers do not set the LDS size of the direct rings.  The
+    // smaller tiers stay whole (their kernels differ by a few registers,
+    // less than an extra launch costs).
     bool odd = false;
     for (int v : ff) odd = odd || (v % 2) != 0;
-    const int key = tier * 4 + (blue ? 2 : 0) + (odd ? 1 : 0);
+    const int key = tier >= 2 ? tier * 4 + (blue ? 2 : 0) + (odd ? 1 : 0) : tier * 4;
     auto ci = class_of.find(key);
     if (ci == class_of.end()) {
       class_of[key] = (int)g->ring_classes.size();
       g->ring_classes.emplace_back();
       g->ring_classes.back().tier = tier;
-      g->ring_classes.back().blue = blue;
-      g->ring_classes.back().odd = odd;
       ci = class_of.find(key);
     }
     RingClass& rc = g->ring_classes[ci->second];
     rc.rings.push_back(r);
+    rc.blue = rc.blue || blue;
+    rc.odd = rc.odd || odd;
     rc.xcap = std::max(rc.xcap, std::max(nf, n0));
     rc.maxn = std::max(rc.maxn, n);
     const int nt = ring_tier_threads(tier);

@@ -112,12 +112,12 @@ struct ShtPlan {
 };
 
 // Rings are launched in classes by FFT length tier (ring_tier_maxfft(t),
-// ring_tier_threads(t) threads per block), Bluestein or direct, and whether
-// the FFT has odd radices.
+// ring_tier_threads(t) threads per block) and, from tier 2 up, by Bluestein
+// or direct transform and whether the FFT has odd radices.
 struct RingClass {
   std::vector<int> rings;
-  bool blue = false;  // the rings of the class use Bluestein's convolution
-  bool odd = false;   // their FFT lengths have radices 3, 5 or 7
+  bool blue = false;  // some ring of the class uses Bluestein's convolution
+  bool odd = false;   // some FFT length of the class has radices 3, 5 or 7
   int tier = 0;
   int xcap = 1;       // complex LDS words for ring data / convolution
   int maxn = 1;       // longest ring in the class
@@ -125,7 +125,7 @@ struct RingClass {
 };
 // tiers: FFT length <= 512 / 1024 / 4096 / 8192 with 128 / 256 / 512 / 1024
 // threads (the longest FFT is a Bluestein convolution of kBlueMax words)
-constexpr int kMaxRingClasses = 16;  // 4 tiers x (Bluestein, odd radix)
+constexpr int kMaxRingClasses = 16;  // at most 4 per tier
 inline int ring_tier_threads(int tier) { return 128 << tier; }
 inline int ring_tier_maxfft(int tier) {
   return tier == 0 ? 512 : tier == 1 ? 1024 : tier == 2 ? 4096 : kBlueMax;

@@ -117,7 +117,7 @@ struct Exec {
   int nwl_rows = 0;
   DevBuf<int4> wl_sys;            // work list over systems (component-space index of P.Lc)
   int nwl_sys = 0;
-  DevBuf<int2> rng_rows, rng_sys;  // per system: (first block, block count) in wl_rows / wl_sys
+  DevBuf<int2> rng_sys;           // per system: (first block, block count) in wl_sys
   DevBuf<double> wpart;           // per work-list block partial dot products
   std::vector<DevBuf<const double*>> vptr;
   std::vector<DevBuf<int>> binfo;
@@ -147,8 +147,8 @@ enum OpKind { OP_A = 0, OP_PI = 1 };
 // act: per-system flags at stride 8 (the PCG scalars' active slot, or the
 // candidate flags of a convergence check); systems whose flag is 0 are left
 // out (their outputs are not written).  NULL: every system.
-// wpart (optional): per block of the back-mix work list, its part of in . out
-// (the system sums are the rng_rows ranges of it).
+// wpart (optional): per block of the system work list (the back-mix runs over
+// it), its part of in . out (the system sums are the rng_sys ranges of it).
 void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act = nullptr,
                 double* wpart = nullptr);
 // wpart (optional): per block of the system work list, its part of r . z

@@ -27,9 +27,10 @@
 // n k = (n^2 + k^2 - (k - n)^2) / 2 as a cyclic convolution of power-of-two
 // length M >= 2n - 1 (filter spectrum precomputed per length on the host).
 // One block per (ring, map); rings are launched in classes by FFT length
-// (<= 512: 128 threads, <= 1024: 256, <= 4096: 512, <= 8192: 1024), by
-// Bluestein or direct transform, and by whether the FFT has odd radices;
-// the half-length path is chosen per ring.
+// (<= 512: 128 threads, <= 1024: 256, <= 4096: 512, <= 8192: 1024) and,
+// for the two longer tiers, by Bluestein or direct transform and whether
+// the FFT has odd radices; the half-length and Bluestein paths are chosen
+// per ring.
 #include "internal.h"
 
 namespace crs {
