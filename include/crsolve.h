@@ -57,7 +57,7 @@ enum {
   CRS_EHIP = -3,          /* a HIP runtime call failed */
   CRS_ENOTCONV = -4,      /* PCG hit maxiter; x holds the last iterate */
   CRS_EBREAKDOWN = -5,    /* PCG breakdown: p.Ap <= 0, r.z <= 0 or non-finite */
-  CRS_EUNSUPPORTED = -6   /* valid request outside what this build supports */
+  CRS_EUNSUPPORTED = -6   /* valid request outside what the library supports */
 };
 
 enum { CRS_PRECOND_NONE = 0, CRS_PRECOND_DIAG = 1, CRS_PRECOND_PINV = 2 };
