@@ -861,7 +861,11 @@ static LegChoice default_choice(int npairs, int L, int nmaps) {
   LegChoice c;
   c.syn_mfma = c.adj_mfma = nmaps >= 4;
   c.syn_r = largest_r(npairs, L, std::min(2, syn_rmax(nmaps)), 4096);
-  c.adj_r = largest_r(npairs, L, 4, 4096);
+  // the adjoint's per-chunk lane reduction wants more waves in flight: four
+  // pairs per lane only from 8192 waves (Nside 512 / L 1024, one map: two
+  // pairs per lane 0.169 ms, four 0.185 ms; Nside 1024 / L 2000: four 0.97,
+  // two 1.03 ms)
+  c.adj_r = largest_r(npairs, L, 4, 8192);
   const long nt = (npairs + 63) / 64;
   c.adj_t = (long)(L + 1) * ((nt + 1) / 2) * ((nmaps + 7) / 8) >= 4096 ? 2 : 1;
   return c;
