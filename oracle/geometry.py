@@ -89,36 +89,55 @@ def healpix(nside):
     return Grid("healpix", z, sint, nphi, phi0, w, {"nside": ns})
 
 
-def _legendre_p_and_dp(n, x):
-    """P_n(x) and P_n'(x) by the Bonnet recurrence (vectorised over x)."""
-    p0 = np.ones_like(x)
+def _legendre_theta(n, th):
+    """P_n(cos th) and P_{n-1}(cos th), vectorised over th.
+
+    Bonnet's recurrence j P_j = (2j - 1) x P_{j-1} - (j - 1) P_{j-2}, rewritten
+    with t = 1 - x = 2 sin^2(th/2) and the differences D_j = P_j - P_{j-1}:
+        j D_j = (j - 1) D_{j-1} - (2j - 1) t P_{j-1}.
+    Taking t from th (not from a rounded x) keeps full relative precision near
+    the poles, where P_{n-1}(x) is steep in x.
+    """
+    t = 2.0 * np.sin(0.5 * th) ** 2
     if n == 0:
-        return p0, np.zeros_like(x)
-    p1 = x.copy()
-    for k in range(2, n + 1):
-        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
-    dp = n * (x * p1 - p0) / (x * x - 1.0)
-    return p1, dp
+        return np.ones_like(th), np.zeros_like(th)
+    prev = np.ones_like(th)
+    p = 1.0 - t
+    d = -t
+    for j in range(2, n + 1):
+        d = ((j - 1) * d - (2 * j - 1) * t * p) / j
+        prev = p
+        p = p + d
+    return p, prev
 
 
 def gauss_legendre_nodes(n, return_sint=False):
-    """Roots of P_n (descending) and the GL weights, by Newton iteration on
-    theta (x = cos theta) so that 1 - x^2 = sin^2 theta keeps full relative
-    precision at the nodes nearest the poles."""
-    k = np.arange(1, n + 1)
-    th = math.pi * (k - 0.25) / (n + 0.5)
+    """Roots of P_n (descending) and the GL weights.
+
+    Newton iteration on theta for the roots with theta <= pi/2 (the others by
+    the symmetry x -> -x), with P_n(cos theta) from _legendre_theta; at a root
+    P_n' = n P_{n-1} / (1 - x^2), so w = 2 sin^2(theta) / (n P_{n-1})^2.
+    """
+    h = (n + 1) // 2
+    k = np.arange(h)
+    th = math.pi * (k + 0.75) / (n + 0.5)
     for _ in range(100):
-        p, dp = _legendre_p_and_dp(n, np.cos(th))
-        # d/dtheta P_n(cos theta) = -sin(theta) P_n'(cos theta)
-        dth = p / (-np.sin(th) * dp)
+        p, pm1 = _legendre_theta(n, th)
+        # d/dtheta P_n(cos theta) = n (cos theta P_n - P_{n-1}) / sin theta
+        dth = p * np.sin(th) / (n * (np.cos(th) * p - pm1))
         th = th - dth
         if np.max(np.abs(dth)) < 1e-16:
             break
-    x = np.cos(th)
-    st = np.sin(th)
-    # at a root P_n' = n P_{n-1} / (1 - x^2), so w = 2 (1 - x^2) / (n P_{n-1})^2
-    pm1, _ = _legendre_p_and_dp(n - 1, x)
-    w = 2.0 * st * st / (n * pm1) ** 2
+    p, pm1 = _legendre_theta(n, th)
+    xn = np.cos(th)
+    if n % 2 == 1:
+        xn[-1] = 0.0
+    sn = np.sin(th)
+    wn = 2.0 * sn * sn / (n * pm1) ** 2
+    m = n // 2  # mirrored (southern) nodes
+    x = np.concatenate([xn, -xn[:m][::-1]])
+    w = np.concatenate([wn, wn[:m][::-1]])
+    st = np.concatenate([sn, sn[:m][::-1]])
     return (x, w, st) if return_sint else (x, w)
 
 

@@ -79,3 +79,31 @@ def test_gauss_legendre_grid_weights_integrate_polynomials():
         assert abs(w @ z ** k - exact) < 1e-13
     for j in range(1, 10):
         assert abs(w @ np.cos(j * phi)) < 1e-13
+
+
+def test_gauss_legendre_polar_weights_at_large_n():
+    """At n = 1001 the nodes nearest the poles sit where P_{n-1}(x) is steep
+    in x; their weights must still be right to about 1e-12 relative (the
+    formula evaluated at a rounded x is off by ~1e-7 there).  Reference:
+    Newton on P_n and the weight 2 (1 - x^2) / (n P_{n-1}(x))^2, all in
+    60-digit decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    n = 1001
+    x, w = geometry.gauss_legendre_nodes(n)
+
+    def p_pair(xd):
+        p0, p1 = Decimal(1), xd
+        for j in range(2, n + 1):
+            p0, p1 = p1, ((2 * j - 1) * xd * p1 - (j - 1) * p0) / j
+        return p1, p0
+
+    for k in (0, 1, n // 3, n // 2, n - 2, n - 1):
+        xd = Decimal(repr(float(x[k])))
+        for _ in range(8):
+            pn, pm = p_pair(xd)
+            xd -= pn / (n * (xd * pn - pm) / (xd * xd - 1))
+        pn, pm = p_pair(xd)
+        wd = 2 * (1 - xd * xd) / (n * pm) ** 2
+        assert abs(float(xd) - x[k]) < 2e-16, k
+        assert abs(float((Decimal(repr(float(w[k]))) - wd) / wd)) < 1e-12, k
