@@ -404,6 +404,8 @@ def main():
     }
     if not a.no_sht_roofline:
         out["sht_roofline"] = sht_roofline(crsolve, torch, dev)
+        # full resolution: Nside 2048 (8192-pixel rings), L = 6000
+        out["sht_roofline"].update(sht_roofline(crsolve, torch, dev, nside=2048, lmax=6000, nmaps_list=(1,), reps=2))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, probs, iters, a.precond)
     print(json.dumps(out), flush=True)

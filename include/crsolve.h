@@ -73,7 +73,9 @@ const char* crs_version(void);
 /* ------------------------------------------------------------------ grids
  * Ring grids of Sect. 2.1 / 2.2: HEALPix RING (Gorski et al. 2005) for sky
  * maps and Gauss-Legendre (roots of P_nrings, north to south, phi0 = 0).
- * Ring lengths are limited to 4096 pixels (Nside <= 1024, nphi <= 4096).
+ * Ring lengths are limited to 8192 pixels (Nside <= 2048, nphi <= 8192); an
+ * odd nphi above 4096 must have no prime factor above 7.  Outside these
+ * limits the constructors return CRS_EUNSUPPORTED.
  */
 int crs_grid_healpix(int nside, crs_grid* out);
 int crs_grid_gauss_legendre(int nrings, int nphi, crs_grid* out);

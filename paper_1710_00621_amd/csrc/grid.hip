@@ -98,48 +98,53 @@ std::vector<double2> bluestein_filter(int n, int M) {
   return b;
 }
 
-// Gauss-Legendre nodes (descending) via Newton iteration on theta.
+// P_n(cos th) and P_{n-1}(cos th) by the Legendre recurrence written for
+// D_j = P_j - P_{j-1} and t = 1 - cos th = 2 sin^2(th / 2):
+//   D_j = ((j - 1) D_{j-1} - (2j - 1) t P_{j-1}) / j,   P_j = P_{j-1} + D_j.
+// It carries the deviation of P_j from P_j(1) = 1 explicitly, with t taken
+// from th, so the values keep full relative precision near the pole (the
+// recurrence in x = cos th inherits the rounding of x, which near the poles
+// moves P_{n-1} by about 1e-6 relative at n = 4000).
+void legendre_theta(int n, double th, double& pn, double& pm1) {
+  const double sh = std::sin(0.5 * th);
+  const double t = 2.0 * sh * sh;
+  double prev = 1.0, p = 1.0 - t, d = -t;  // P_0, P_1, D_1
+  for (int j = 2; j <= n; ++j) {
+    d = ((j - 1.0) * d - (2.0 * j - 1.0) * t * p) / j;
+    prev = p;
+    p += d;
+  }
+  pn = n == 0 ? 1.0 : p;
+  pm1 = n == 0 ? 0.0 : prev;
+}
+
+// Gauss-Legendre nodes (descending) and weights: Newton iteration on theta
+// for the nodes of the northern half (theta <= pi / 2), the southern half by
+// symmetry; weights w = 2 sin^2 th / (n P_{n-1}(cos th))^2.
 void gl_nodes(int n, std::vector<double>& z, std::vector<double>& st, std::vector<double>& w) {
   z.resize(n);
   st.resize(n);
   w.resize(n);
-  for (int k = 0; k < n; ++k) {
+  for (int k = 0; k < (n + 1) / 2; ++k) {
     double th = M_PI * (k + 0.75) / (n + 0.5);
-    double x = 0, pn = 0, pn1 = 0;
+    double pn = 0, pm1 = 0;
     for (int it = 0; it < 100; ++it) {
-      x = std::cos(th);
-      double p0 = 1.0, p1 = x;
-      for (int j = 2; j <= n; ++j) {
-        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
-        p0 = p1;
-        p1 = p2;
-      }
-      pn = (n == 1) ? x : p1;
-      pn1 = (n == 1) ? 1.0 : p0;
-      // dP_n/dx = n (x P_n - P_{n-1}) / (x^2 - 1); d/dtheta = -sin * dP/dx
-      double s = std::sin(th);
-      double dpdx = n * (x * pn - pn1) / (x * x - 1.0);
-      double dth = pn / (-s * dpdx);
+      legendre_theta(n, th, pn, pm1);
+      // d/dth P_n(cos th) = n (cos th P_n - P_{n-1}) / sin th
+      const double dth = pn * std::sin(th) / (n * (std::cos(th) * pn - pm1));
       th -= dth;
       if (std::fabs(dth) < 1e-16) break;
     }
-    x = std::cos(th);
-    double s = std::sin(th);
-    // P_{n-1}(x) at the converged node
-    double p0 = 1.0, p1 = x;
-    if (n == 1) p1 = 1.0;
-    else {
-      for (int j = 2; j <= n - 1; ++j) {
-        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
-        p0 = p1;
-        p1 = p2;
-      }
-      if (n == 2) p1 = x;
-    }
-    double pm1 = (n == 1) ? 1.0 : p1;
+    legendre_theta(n, th, pn, pm1);
+    const double s = std::sin(th);
+    const double x = (2 * k + 1 == n) ? 0.0 : std::cos(th);
+    const double wk = 2.0 * s * s / ((n * pm1) * (n * pm1));
     z[k] = x;
     st[k] = s;
-    w[k] = 2.0 * s * s / ((n * pm1) * (n * pm1));
+    w[k] = wk;
+    z[n - 1 - k] = -x;
+    st[n - 1 - k] = s;
+    w[n - 1 - k] = wk;
   }
 }
 
@@ -157,7 +162,7 @@ void grid_finalize(crs_grid g, hipStream_t s) {
   g->npix = off;
   for (int r = 0; r < nr; ++r)
     CRS_CHECK(g->nphi[r] <= kMaxRing, CRS_EUNSUPPORTED,
-              "ring length above 4096 pixels is not supported");
+              "ring length above 8192 pixels is not supported");
   // Per ring: the complex FFT that the ring kernels run.  Even Nphi uses a
   // half-length complex transform (two real samples per complex word); a
   // length whose largest prime factor exceeds 7 goes through Bluestein's
@@ -192,6 +197,8 @@ void grid_finalize(crs_grid g, hipStream_t s) {
         bfoff[r] = it->second;
       }
     }
+    CRS_CHECK(nf <= kBlueMax, CRS_EUNSUPPORTED,
+              "ring FFT above 8192 points (an odd ring longer than 4096 pixels with a prime factor above 7)");
     auto ff = factorize(nf);
     CRS_CHECK((int)ff.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
     nfac[r] = (int)ff.size();
@@ -537,7 +544,7 @@ int crs_grid_healpix(int nside, crs_grid* out) {
   return guarded([&] {
     CRS_CHECK(out != nullptr, CRS_EINVAL, "out is NULL");
     CRS_CHECK(nside >= 1, CRS_EINVAL, "nside must be >= 1");
-    CRS_CHECK(nside <= 1024, CRS_EUNSUPPORTED, "nside above 1024 is not supported");
+    CRS_CHECK(nside <= 2048, CRS_EUNSUPPORTED, "nside above 2048 is not supported");
     auto g = std::make_unique<crs_grid_s>();
     CRS_HIP(hipGetDevice(&g->device));
     build_healpix(g.get(), nside);
@@ -551,7 +558,15 @@ int crs_grid_gauss_legendre(int nrings, int nphi, crs_grid* out) {
   return guarded([&] {
     CRS_CHECK(out != nullptr, CRS_EINVAL, "out is NULL");
     CRS_CHECK(nrings >= 1 && nphi >= 1, CRS_EINVAL, "nrings and nphi must be >= 1");
-    CRS_CHECK(nphi <= kMaxRing, CRS_EUNSUPPORTED, "nphi above 4096 is not supported");
+    CRS_CHECK(nphi <= kMaxRing, CRS_EUNSUPPORTED, "nphi above 8192 is not supported");
+    // an odd ring is transformed at full length: above 4096 pixels its length
+    // must be 7-smooth (Bluestein's convolution would exceed 8192 points)
+    if (nphi % 2 == 1 && nphi > kMaxRing / 2) {
+      int n = nphi;
+      for (int p : {3, 5, 7})
+        while (n % p == 0) n /= p;
+      CRS_CHECK(n == 1, CRS_EUNSUPPORTED, "odd nphi above 4096 must have no prime factor above 7");
+    }
     auto g = std::make_unique<crs_grid_s>();
     CRS_HIP(hipGetDevice(&g->device));
     build_gl(g.get(), nrings, nphi);

@@ -93,7 +93,7 @@ struct DevBuf {
   void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
 };
 
-constexpr int kMaxRing = 4096;   // ring FFT length limit (LDS resident)
+constexpr int kMaxRing = 8192;   // pixels per ring (the FFT stays LDS resident)
 constexpr int kMaxFactors = 16;  // radices per ring length
 constexpr int kBlueMax = 8192;   // longest Bluestein convolution (power of two)
 

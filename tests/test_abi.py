@@ -45,9 +45,10 @@ def test_invalid_arguments_rejected_on_host():
     h = ctypes.c_void_p()
     assert lib.crs_grid_healpix(0, ctypes.byref(h)) == L.CRS_EINVAL
     assert lib.crs_grid_healpix(4, None) == L.CRS_EINVAL
-    assert lib.crs_grid_healpix(2048, ctypes.byref(h)) == L.CRS_EUNSUPPORTED
+    assert lib.crs_grid_healpix(4096, ctypes.byref(h)) == L.CRS_EUNSUPPORTED
     assert lib.crs_grid_gauss_legendre(0, 5, ctypes.byref(h)) == L.CRS_EINVAL
-    assert lib.crs_grid_gauss_legendre(5, 5000, ctypes.byref(h)) == L.CRS_EUNSUPPORTED
+    assert lib.crs_grid_gauss_legendre(5, 9000, ctypes.byref(h)) == L.CRS_EUNSUPPORTED
+    assert lib.crs_grid_gauss_legendre(5, 4099, ctypes.byref(h)) == L.CRS_EUNSUPPORTED  # odd prime
     assert lib.crs_model_create(None, None, ctypes.byref(h)) == L.CRS_EINVAL
     assert lib.sht_synth(None, 4, 1, None, 25, None, 10, None) == L.CRS_EINVAL
     assert lib.apply_A(None, 1, None, None, None) == L.CRS_EINVAL

@@ -288,3 +288,52 @@ def test_ring_launch_classes_agree(monkeypatch):
         one_alm = crsolve.sht_adjoint(g, lmax, maps[j:j + 1]).cpu().numpy()
         assert _rel(one_map[0], many_map[j]) < 1e-13, j
         assert _rel(one_alm[0], many_alm[j]) < 1e-13, j
+
+
+def test_gl_round_trip_large():
+    """Y^T W Y = I at L = 4000 on the 4001 x 8192 Gauss-Legendre grid (exact
+    quadrature: 4001 nodes integrate degree 2L, 8192 >= 2L + 1 points per
+    ring): rings of 8192 pixels, the recurrence deep into underflow at high
+    m.  Two transforms, so twice the per-transform bound."""
+    torch, crsolve = _setup()
+    nring, nphi, lmax = 4001, 8192, 4000
+    print(f"case GL round trip {nring}x{nphi} lmax={lmax}", flush=True)
+    g = crsolve.Grid.gauss_legendre(nring, nphi)
+    w = torch.tensor(g.weights(), device="cuda")
+    gen = torch.Generator(device="cpu").manual_seed(41)
+    a = torch.randn(1, sht.nalm(lmax), generator=gen, dtype=torch.float64).to("cuda")
+    back = crsolve.sht_adjoint(g, lmax, crsolve.sht_synth(g, lmax, a) * w)
+    err = float((back - a).abs().max() / a.abs().max())
+    print(f"round trip max rel error {err:.3e}", flush=True)
+    assert err < 2 * SHT_TOL
+
+
+def test_sht_nside2048_l6000_sampled():
+    """Full resolution (Nside 2048: 8192-pixel rings, L = 6000): the adjoint
+    on sampled m for every ring against the oracle, and the synthesis tied to
+    it by the adjoint identity <Y x, y> = <x, Y^T y>."""
+    torch, crsolve = _setup()
+    nside, lmax = 2048, 6000
+    print(f"case full resolution nside={nside} lmax={lmax}", flush=True)
+    g = crsolve.Grid.healpix(nside)
+    og = geometry.healpix(nside)
+    rng = np.random.default_rng(43)
+    maps = rng.standard_normal((1, og.npix))
+    dev = torch.device("cuda")
+    y = torch.tensor(maps, device=dev)
+    got_a = crsolve.sht_adjoint(g, lmax, y)
+    ms = [0, 1, 3000, lmax - 1, lmax]
+    ref_a = _sampled_adjoint_ref(og, lmax, maps, ms)
+    ga = got_a.cpu().numpy()
+    for m in ms:
+        n = lmax - m + 1
+        o = sht.m_offset(lmax, m)
+        assert _rel(ga[:, o:o + n], ref_a[m][0]) < SHT_TOL, m
+        if m > 0:
+            assert _rel(ga[:, o + n:o + 2 * n], ref_a[m][1]) < SHT_TOL, m
+    ell = sht.lm_arrays(lmax)[0]
+    x = torch.tensor(rng.standard_normal((1, sht.nalm(lmax))) / np.sqrt(1.0 + ell), device=dev)
+    yx = crsolve.sht_synth(g, lmax, x)
+    lhs = float((yx * y).sum())
+    rhs = float((x * got_a).sum())
+    assert abs(lhs - rhs) / float(yx.norm() * y.norm()) < 1e-13
