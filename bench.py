@@ -264,8 +264,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: every GPU box here has one MI355X and the solver does "
-              "not shard across GPUs (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single MI355X and does not shard "
+              "across GPUs (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if a.precond is None:
         a.precond = "diag" if a.workload == "batched" else "pinv"
