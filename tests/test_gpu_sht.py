@@ -37,6 +37,8 @@ CASES = [
     (("gl", 5, 4093), 40, 1),    # odd prime ring length above 2048: full-length Bluestein
     (("gl", 9, 1), 4, 1),        # one pixel per ring: everything aliases onto m = 0
     (("gl", 7, 2046), 1100, 1),  # even length 2 * 3 * 11 * 31: half-length Bluestein
+    (("gl", 5, 4375), 40, 1),    # odd 5^4 * 7 above 4096: full-length direct FFT, longest tier
+    (("gl", 3, 8190), 30, 2),    # 8190 = 2 * 4095 (factor 13): Bluestein of 8192 points
 ]
 
 
