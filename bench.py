@@ -119,10 +119,15 @@ def sht_roofline(crsolve, torch, dev, nside=1024, lmax=2000, nmaps_list=(1, 6), 
             avg_ms = st["ms"] / max(1, st["launches"])
             work = st["work"] / max(1, st["launches"])
             if fam == "ring_fft":
-                res[fam] = {"avg_ms": avg_ms, "GBs": work / (avg_ms * 1e-3) / 1e9}
+                gbs = work / (avg_ms * 1e-3) / 1e9
+                res[fam] = {"avg_ms": avg_ms, "GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
             else:
+                cnt = crsolve.kernel_work_counts(fam)
+                n = max(1, st["launches"])
                 tf = work / (avg_ms * 1e-3) / 1e12
-                res[fam] = {"avg_ms": avg_ms, "TFLOPs": tf, "frac": tf / FP64_PEAK_TFLOPS}
+                res[fam] = {"avg_ms": avg_ms, "TFLOPs": tf, "frac": tf / FP64_PEAK_TFLOPS,
+                            "frac_nominal": cnt["nominal"] / n / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                            "frac_evaluated": cnt["evaluated"] / n / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
         out[f"nside{nside}_l{lmax}_nmaps{nm}"] = res
     return out
 
@@ -135,6 +140,17 @@ def _oracle_model(prob, taus):
              for b, bm, t in zip(prob["bands"], inputs.beams(prob), taus)]
     comps = [{"lmax": c["lmax"], "invcl": icl} for c, icl in zip(prob["comps"], inputs.priors(prob))]
     return OModel(bands, comps, prob["q"])
+
+
+def _blas_threads():
+    """Threads the oracle's numpy BLAS runs with (its matrix products are the
+    multi-threaded part of the oracle)."""
+    try:
+        from threadpoolctl import threadpool_info
+        n = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        return int(n)
+    except Exception:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
 def _sht_work(prob):
@@ -156,7 +172,7 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
     from oracle import geometry, precond as opc
     from paper_1710_00621_amd import inputs
 
-    nthreads = os.cpu_count() or 1
+    nthreads = _blas_threads()
     if name != "batched":
         scale = 8 if name == "masked" else 2
         prob = inputs.make_problem(name, scale=scale)
@@ -181,27 +197,39 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
                 "sample": (f"one oracle PCG iteration (apply_A + M_{precond}) of the {name} recipe "
                            f"at 1/{scale} resolution took {dt:.1f} s; scaled by the Legendre work ratio "
                            f"{ratio:.2f} and by the GPU's {gpu_iters[0]} iterations (extrapolated)")}
-    t_total = 0.0
-    est, used = [], []
-    order = sorted(range(len(probs)), key=lambda i: probs[i]["model"].n)
-    for i in order:
-        if t_total > budget_s:
-            break
-        p = probs[i]
-        om = _oracle_model(p["prob"], p["taus"])
+    # batched: one problem of each Nside_max tier (the first of the tier), at
+    # full resolution for the 64 and 128 tiers and at half resolution for the
+    # 256 tier (scaled by the Legendre work ratio); every problem's estimate is
+    # its tier's time per iteration times its own GPU iteration count
+    per_iter = {}
+    notes = []
+    for tier_i, tier in enumerate((64, 128, 256)):
+        p = probs[tier_i]
+        scale = 2 if tier == 256 else 1
+        prob = inputs.make_problem("batched", scale=scale, index=tier_i)
+        cache = {}
+
+        def centres(spec):
+            if spec not in cache:
+                cache[spec] = geometry.make_grid(spec).pixel_centres()
+            return cache[spec]
+
+        taus = p["taus"] if scale == 1 else inputs.inverse_noise_maps(prob, centres)
+        om = _oracle_model(prob, taus)
         M = opc.PseudoInversePrecond(om) if precond == "pinv" else opc.DiagonalPrecond(om)
         v = np.random.default_rng(0).standard_normal(om.n)
         t0 = time.perf_counter()
         om.apply_A(v)
         M(v)
         dt = time.perf_counter() - t0
-        t_total += dt
-        est.append(dt * gpu_iters[i])
-        used.append(i)
+        ratio = _sht_work(p["prob"]) / _sht_work(prob)
+        per_iter[tier] = dt * ratio
+        notes.append(f"Nside_max {tier}: {dt:.2f} s at 1/{scale} resolution x {ratio:.2f}")
+    est = [per_iter[(64, 128, 256)[i % 3]] * gpu_iters[i] for i in range(len(probs))]
     return {"value": 1e3 * float(np.mean(est)), "unit": "ms/RHS", "cores": nthreads, "kind": "oracle",
-            "sample": (f"one oracle PCG iteration (apply_A + M_{precond}) timed on {len(used)} of the "
-                       f"smallest problems (indices {used}), times each problem's GPU iteration "
-                       f"count; extrapolated per RHS")}
+            "sample": ("one oracle PCG iteration (apply_A + M_" + precond + ") per Nside_max tier (" +
+                       "; ".join(notes) + " by the Legendre work ratio), times each of the 64 problems' "
+                       "GPU iteration counts; extrapolated per RHS")}
 
 
 def _traffic(kernel, workload):
@@ -232,16 +260,35 @@ def _traffic(kernel, workload):
 
 
 def _roofline(crsolve, ms_total, workload):
+    """Dominant Legendre family over the timed region.  achieved = its flops
+    counted over the (ring pair, l, m) triples whose |lambda| reaches the
+    float64 range, each launch credited with the maps still active, divided
+    by its summed launch time (HIP events on the launch stream, recorded in
+    the captured graphs).  The nominal and the kernels' own (>= 2^-100)
+    triple counts are given beside it."""
     fam = {f: crsolve.kernel_stats(f) for f in ("legendre_synth", "legendre_adjoint", "ring_fft")}
     dom = max(("legendre_synth", "legendre_adjoint"), key=lambda f: fam[f]["ms"])
     st = fam[dom]
-    achieved = st["work"] / max(1e-30, st["ms"] * 1e-3) / 1e12
+    secs = max(1e-30, st["ms"] * 1e-3)
+    achieved = st["work"] / secs / 1e12
+    counts = crsolve.kernel_work_counts(dom)
+    launches = max(1, st["launches"])
     ring = fam["ring_fft"]
+    other = "legendre_adjoint" if dom == "legendre_synth" else "legendre_synth"
+    so = fam[other]
     return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": _traffic(dom, workload),
-            "avg_launch_ms": st["ms"] / max(1, st["launches"]), "launches": st["launches"],
+            "avg_launch_ms": st["ms"] / launches, "launches": st["launches"],
+            "flops_per_launch": {"fp64_range": counts["fp64"] / launches,
+                                 "nominal": counts["nominal"] / launches,
+                                 "evaluated": counts["evaluated"] / launches},
+            "frac_nominal": counts["nominal"] / secs / 1e12 / FP64_PEAK_TFLOPS,
+            "frac_evaluated": counts["evaluated"] / secs / 1e12 / FP64_PEAK_TFLOPS,
             "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
             / max(1e-9, ms_total),
+            other: {"TFLOP/s": so["work"] / max(1e-30, so["ms"] * 1e-3) / 1e12,
+                    "frac": so["work"] / max(1e-30, so["ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                    "avg_launch_ms": so["ms"] / max(1, so["launches"])},
             "ring_fft": {"GB/s": ring["work"] / max(1e-30, ring["ms"] * 1e-3) / 1e9,
                          "frac_hbm": ring["work"] / max(1e-30, ring["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "share_of_step": ring["ms"] / max(1e-9, ms_total)}}
@@ -267,6 +314,8 @@ def main():
     ap.add_argument("--precond", default=None, choices=["pinv", "diag"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=5000)
+    ap.add_argument("--pinv-maxiter", type=int, default=3000,
+                    help="batched workload: iteration cap of the reported pseudo-inverse solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sht-roofline", action="store_true")
     ap.add_argument("--no-multires", action="store_true")
@@ -351,6 +400,25 @@ def main():
         extra["plain_ms_per_rhs"] = plain_rhs
         extra["speedup_batched_over_plain"] = plain_rhs / per_rhs
         extra["plain_iterations_sum"] = int(sum(it_p))
+        # the same batch with the pseudo-inverse preconditioner (the paper's
+        # preconditioner; it degrades under masks), one solve, bounded
+        if a.precond != "pinv":
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            d = [[t[0] for t in p["d"]] for p in probs]
+            xs_pi, info_pi = batch.solve(d=d, seeds=[p["prob"]["seed"] for p in probs], mode="cr",
+                                         precond="pinv", rtol=a.rtol, maxiter=a.pinv_maxiter,
+                                         use_graph=True, raise_on_error=False)
+            torch.cuda.synchronize()
+            t_pi = (time.perf_counter() - tq) * 1e3
+            extra["batched_pinv"] = {
+                "ms_per_rhs": t_pi / nrhs, "status": info_pi["status"],
+                "converged": info_pi["status"] == 0, "iterations_max": max(info_pi["iters"]),
+                "iterations_mean": sum(info_pi["iters"]) / nrhs,
+                "relres_max": max(info_pi["relres"]), "maxiter": a.pinv_maxiter,
+                "note": "M_PI on the same masked batch (tau^+ = 0 in the mask); a time to solution "
+                        "only when converged"}
+            log(f"batched pinv: {extra['batched_pinv']}")
         # the pseudo-inverse preconditioner on the smallest problem (bounded)
         if a.precond != "pinv":
             small = min(probs, key=lambda p: p["model"].n)

@@ -223,6 +223,24 @@ int crs_model_project(crs_model m, int nrhs, const double* x, double* const* map
  *                  nbands device pointers, each nrhs x npix_nu; NULL entries are zero).
  */
 int apply_prior_inv(crs_model m, int nrhs, const double* x, double* y, crs_stream s);
+/* The terms of a Wiener-filter loss L = 1/2 x^T S^-1 x + chi^2 (the prior
+ * term and the data misfit of the posterior of Sect. 2.3) and its gradient
+ * with respect to the data maps:
+ * crs_prior_quad:   y = S^-1 x and val[r] = 1/2 x_r^T S^-1 x_r (val: device, nrhs).
+ * crs_chi2:         res_nu = d_nu - P_nu x (res: host array of nbands device
+ *                   pointers, each nrhs x npix_nu, written) and
+ *                   val[r] = sum_nu res_nu^T N_nu^-1 res_nu (device, nrhs);
+ *                   d as in build_rhs (NULL entries are zero).
+ * crs_noise_weight: out_nu = scale N_nu^-1 in_nu, per band (in / out as res;
+ *                   NULL in entries are zero).  With in = P lam it gives
+ *                   dL/dd through the right-hand side; with in = res and
+ *                   scale 2 the chi-square's own dL/dd.
+ * These calls synchronise the stream before returning. */
+int crs_prior_quad(crs_model m, int nrhs, const double* x, double* y, double* val, crs_stream s);
+int crs_chi2(crs_model m, int nrhs, const double* x, const double* const* d, double* const* res,
+             double* val, crs_stream s);
+int crs_noise_weight(crs_model m, int nrhs, double scale, const double* const* in, double* const* out,
+                     crs_stream s);
 int apply_dA_dmix(crs_model m, int nrhs, const double* lam, const double* x, double* dq,
                   crs_stream s);
 int apply_db_dmix(crs_model m, int nrhs, const double* lam, const double* const* d, double* dq,
@@ -268,6 +286,14 @@ int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const 
 int crs_set_profiling(int on);
 int crs_kernel_stats(const char* family, int64_t* launches, double* total_ms,
                      double* total_work);
+/* The summed work of a family counted three ways (work3, host array of 3):
+ * [0] Legendre flops over the (ring pair, l, m) triples whose |lambda_lm|
+ * reaches the float64 normal range (the figure crs_kernel_stats reports),
+ * [1] over all triples (nominal), [2] over the triples the kernels evaluate
+ * (|lambda_lm| >= 2^-100).  Legendre flops per triple: 4 for the recurrence
+ * plus 4 per map.  Launches on finished systems are credited with the work
+ * of the maps still active.  ring_fft: bytes in all three. */
+int crs_kernel_work_counts(const char* family, double* work3);
 int crs_kernel_stats_reset(void);
 
 #ifdef __cplusplus

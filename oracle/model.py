@@ -57,15 +57,16 @@ class Model:
                  for k, c in enumerate(self.comps)]
         return self.join(parts)
 
-    def project(self, x, nu):
-        """P_nu x: pixel map of band nu."""
+    def project(self, x, nu, ms=None):
+        """P_nu x: pixel map of band nu (ms: only these m are synthesised, the
+        other m of x taken as zero)."""
         b = self.bands[nu]
-        return sht.synth(b["grid"], b["lmax"], self.to_band(x, nu))
+        return sht.synth(b["grid"], b["lmax"], self.to_band(x, nu), ms=ms)
 
-    def project_t(self, f, nu):
-        """P_nu^T f for a pixel map f of band nu."""
+    def project_t(self, f, nu, ms=None):
+        """P_nu^T f for a pixel map f of band nu (ms: only these m computed)."""
         b = self.bands[nu]
-        return self.from_band(sht.adjoint(b["grid"], b["lmax"], f), nu)
+        return self.from_band(sht.adjoint(b["grid"], b["lmax"], f, ms=ms), nu)
 
     def apply_prior_inv(self, x):
         """S^-1 x (diagonal, C_{k,l}^-1 per coefficient)."""
@@ -73,9 +74,19 @@ class Model:
                  for k, (c, xk) in enumerate(zip(self.comps, self.split(x)))]
         return self.join(parts)
 
-    def apply_A(self, x):
-        """A x = S^-1 x + sum_nu P_nu^T N_nu^-1 P_nu x (eq:A)."""
+    def apply_A(self, x, ms_in=None, ms_out=None):
+        """A x = S^-1 x + sum_nu P_nu^T N_nu^-1 P_nu x (eq:A).
+
+        ms_in / ms_out (optional, for sampled checks at large sizes): x is
+        nonzero only at the m in ms_in, and only the outputs at the m in
+        ms_out are wanted (the others are returned as zero)."""
         y = self.apply_prior_inv(x)
+        if ms_out is not None:
+            keep = np.zeros(self.n, dtype=bool)
+            for k, c in enumerate(self.comps):
+                mm = sht.lm_arrays(c["lmax"])[1]
+                keep[self.offsets[k]:self.offsets[k + 1]] = np.isin(mm, list(ms_out))
+            y = np.where(keep, y, 0.0)
         for nu, b in enumerate(self.bands):
-            y = y + self.project_t(b["tau"] * self.project(x, nu), nu)
+            y = y + self.project_t(b["tau"] * self.project(x, nu, ms=ms_in), nu, ms=ms_out)
         return y

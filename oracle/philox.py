@@ -69,19 +69,31 @@ def raw_words(seed, stream, rhs, n):
     return np.stack(w, axis=1).reshape(-1)[:n]
 
 
-def normals(seed, stream, rhs, n):
-    """n standard normal variates of stream (seed, stream, rhs)."""
-    nblk = (n + 3) // 4
-    w = raw_words(seed, stream, rhs, 4 * nblk)
-    u = ((w >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
-    u = u.reshape(nblk, 4)
-    out = np.empty((nblk, 4))
+def uniforms(words):
+    """64-bit words -> uniforms ((w >> 11) + 0.5) 2^-53, strictly inside (0, 1)."""
+    w = np.asarray(words, dtype=np.uint64)
+    return ((w >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def box_muller(u):
+    """Uniforms [nblk, 4] -> normals [nblk, 4]: pairs (u0, u1) and (u2, u3);
+    the first of a pair sets the radius sqrt(-2 ln u), the second the angle
+    2 pi u, and the pair's outputs are radius * (cos, sin) of that angle."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.empty_like(u)
     for a, b in ((0, 1), (2, 3)):
         rad = np.sqrt(-2.0 * np.log(u[:, a]))
         ang = 2.0 * np.pi * u[:, b]
         out[:, a] = rad * np.cos(ang)
         out[:, b] = rad * np.sin(ang)
-    return out.reshape(-1)[:n]
+    return out
+
+
+def normals(seed, stream, rhs, n):
+    """n standard normal variates of stream (seed, stream, rhs)."""
+    nblk = (n + 3) // 4
+    w = raw_words(seed, stream, rhs, 4 * nblk)
+    return box_muller(uniforms(w).reshape(nblk, 4)).reshape(-1)[:n]
 
 
 # Stream identifiers used by the constrained-realization right-hand side.

@@ -72,13 +72,25 @@ def _as2d(a):
     return (a[None, :], True) if a.ndim == 1 else (a, False)
 
 
-def _phase_from_alm(grid, lmax, alm):
+def _mlist(lmax, ms):
+    """The m values to evaluate: all of 0..lmax, or a sorted subset (m above
+    lmax carry no coefficients and are dropped)."""
+    if ms is None:
+        return list(range(lmax + 1))
+    out = sorted(set(int(m) for m in ms))
+    if out and out[0] < 0:
+        raise ValueError("negative m")
+    return [m for m in out if m <= lmax]
+
+
+def _phase_from_alm(grid, lmax, alm, ms=None):
     """F^c, F^s of shape [nmaps, nring, lmax+1] (the Legendre half of Y)."""
     nmaps = alm.shape[0]
     Fc = np.zeros((nmaps, grid.nring, lmax + 1))
     Fs = np.zeros((nmaps, grid.nring, lmax + 1))
     sweep = LegendreSweep(grid.z, grid.sint, lmax)
-    for m in range(lmax + 1):
+    for m in _mlist(lmax, ms):
+        sweep.skip_to(m)
         lam = sweep.table(m)  # [nring, lmax-m+1]
         n = lmax - m + 1
         if m == 0:
@@ -91,41 +103,49 @@ def _phase_from_alm(grid, lmax, alm):
     return Fc, Fs
 
 
-def synth(grid, lmax, alm):
-    """Y alm: pixel maps [nmaps, npix] (or [npix] for a 1-D input)."""
+def synth(grid, lmax, alm, ms=None):
+    """Y alm: pixel maps [nmaps, npix] (or [npix] for a 1-D input).
+
+    ms (optional): evaluate only these m; the other m blocks of alm are taken
+    as zero (the sum over m simply leaves them out)."""
     alm, squeeze = _as2d(alm)
     if alm.shape[1] != nalm(lmax):
         raise ValueError("alm has the wrong length for lmax")
-    Fc, Fs = _phase_from_alm(grid, lmax, alm)
+    Fc, Fs = _phase_from_alm(grid, lmax, alm, ms)
     out = np.zeros((alm.shape[0], grid.npix))
-    ms = np.arange(lmax + 1)
+    msel = np.array(_mlist(lmax, ms), dtype=np.int64)
     for r in range(grid.nring):
         phi = grid.ring_phi(r)
-        arg = np.outer(phi, ms)
+        arg = np.outer(phi, msel)
         o, n = grid.offset[r], grid.nphi[r]
-        out[:, o:o + n] = Fc[:, r, :] @ np.cos(arg).T + Fs[:, r, :] @ np.sin(arg).T
+        out[:, o:o + n] = Fc[:, r, msel] @ np.cos(arg).T + Fs[:, r, msel] @ np.sin(arg).T
     return out[0] if squeeze else out
 
 
-def adjoint(grid, lmax, maps):
-    """Y^T maps: harmonic vectors [nmaps, (lmax+1)^2]."""
+def adjoint(grid, lmax, maps, ms=None):
+    """Y^T maps: harmonic vectors [nmaps, (lmax+1)^2].
+
+    ms (optional): compute only the outputs of these m (the other m blocks of
+    the result are left zero)."""
     maps, squeeze = _as2d(maps)
     if maps.shape[1] != grid.npix:
         raise ValueError("map has the wrong number of pixels")
     nmaps = maps.shape[0]
+    msel = np.array(_mlist(lmax, ms), dtype=np.int64)
     Hc = np.zeros((nmaps, grid.nring, lmax + 1))
     Hs = np.zeros((nmaps, grid.nring, lmax + 1))
-    ms = np.arange(lmax + 1)
     for r in range(grid.nring):
         phi = grid.ring_phi(r)
-        arg = np.outer(phi, ms)
+        arg = np.outer(phi, msel)
         o, n = grid.offset[r], grid.nphi[r]
         f = maps[:, o:o + n]
-        Hc[:, r, :] = f @ np.cos(arg)
-        Hs[:, r, :] = f @ np.sin(arg)
+        Hc[:, r, msel] = f @ np.cos(arg)
+        Hs[:, r, msel] = f @ np.sin(arg)
     out = np.zeros((nmaps, nalm(lmax)))
     sweep = LegendreSweep(grid.z, grid.sint, lmax)
-    for m in range(lmax + 1):
+    for m in msel:
+        m = int(m)
+        sweep.skip_to(m)
         lam = sweep.table(m)
         n = lmax - m + 1
         if m == 0:

@@ -80,6 +80,10 @@ _SIGS = {
                                                c_double_p, vp]),
     "crs_model_project": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), vp]),
     "apply_prior_inv": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+    "crs_prior_quad": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
+    "crs_chi2": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp]),
+    "crs_noise_weight": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), vp]),
     "apply_dA_dmix": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
     "apply_db_dmix": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.POINTER(vp), vp, vp]),
     "crs_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]),
@@ -93,6 +97,7 @@ _SIGS = {
                                           ctypes.c_int64, vp, vp]),
     "crs_set_profiling": (ctypes.c_int, [ctypes.c_int]),
     "crs_kernel_stats": (ctypes.c_int, [ctypes.c_char_p, c_int64_p, c_double_p, c_double_p]),
+    "crs_kernel_work_counts": (ctypes.c_int, [ctypes.c_char_p, c_double_p]),
     "crs_kernel_stats_reset": (ctypes.c_int, []),
 }
 

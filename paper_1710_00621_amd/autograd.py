@@ -99,10 +99,26 @@ def prior_inv(model, x):
     return y
 
 
-def _tau(model, nu, device):
-    if getattr(model, "_tau_dev", None) is None:
-        model._tau_dev = [torch.tensor(t, dtype=torch.float64, device=device) for t in model.taus]
-    return model._tau_dev[nu]
+class _Mixing:
+    """Sets the model's mixing matrix to q for the duration of a block and
+    puts the previous one back (a backward pass may run after other forwards
+    have set another q on the same model)."""
+
+    def __init__(self, model, q):
+        self.model, self.q = model, q.detach().cpu().numpy()
+
+    def __enter__(self):
+        self.prev = getattr(self.model, "_q_now", None)
+        if self.prev is None or not (self.prev.shape == self.q.shape and (self.prev == self.q).all()):
+            self.model.set_mixing(self.q)
+            self.model._q_now = self.q
+        return self
+
+    def __exit__(self, *exc):
+        if self.prev is not None and self.model._q_now is not self.prev:
+            self.model.set_mixing(self.prev)
+            self.model._q_now = self.prev
+        return False
 
 
 class WienerSolve(torch.autograd.Function):
@@ -110,32 +126,34 @@ class WienerSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, q, model, opts, *d):
-        model.set_mixing(q.detach().cpu().numpy())
-        b = model.build_rhs(d=[t.detach().unsqueeze(0) for t in d])[0]
-        x, info = model.pcg(b, precond=opts.get("precond", "pinv"), rtol=opts.get("rtol", 1e-12),
-                            maxiter=opts.get("maxiter", 5000))
+        qd = q.detach()
+        with _Mixing(model, qd):
+            b = model.build_rhs(d=[t.detach().unsqueeze(0) for t in d])[0]
+            x, info = model.pcg(b, precond=opts.get("precond", "pinv"), rtol=opts.get("rtol", 1e-12),
+                                maxiter=opts.get("maxiter", 5000))
         ctx.model, ctx.opts, ctx.qdev = model, opts, q.device
-        ctx.save_for_backward(x, *[t.detach() for t in d])
+        ctx.save_for_backward(qd, x, *[t.detach() for t in d])
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        x, *d = ctx.saved_tensors
+        q, x, *d = ctx.saved_tensors
         model, opts = ctx.model, ctx.opts
-        lam, _ = model.pcg(gx.contiguous(), precond=opts.get("precond", "pinv"),
-                           rtol=opts.get("rtol", 1e-12), maxiter=opts.get("maxiter", 5000))
-        grad_q = db_dmix(model, lam, d) + dA_dmix(model, lam, x)
-        proj = model.project(lam)
-        grad_d = [_tau(model, nu, lam.device) * proj[nu] for nu in range(model.nbands)]
+        with _Mixing(model, q):
+            lam, _ = model.pcg(gx.contiguous(), precond=opts.get("precond", "pinv"),
+                               rtol=opts.get("rtol", 1e-12), maxiter=opts.get("maxiter", 5000))
+            grad_q = db_dmix(model, lam, d) + dA_dmix(model, lam, x)
+            # dL/dd_nu = N^-1 P_nu lam
+            grad_d = model.noise_weight(model.project(lam))
         return (grad_q.to(ctx.qdev), None, None, *grad_d)
 
 
 class PriorQuad(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, model):
-        y = prior_inv(model, x.detach())
+        val, y = model.prior_quad(x.detach())
         ctx.save_for_backward(y)
-        return 0.5 * torch.dot(x.detach(), y)
+        return val
 
     @staticmethod
     def backward(ctx, g):
@@ -144,26 +162,27 @@ class PriorQuad(torch.autograd.Function):
 
 
 class Chi2(torch.autograd.Function):
-    """sum_nu (d_nu - P_nu x)^T N_nu^-1 (d_nu - P_nu x) at the model's current q."""
+    """sum_nu (d_nu - P_nu x)^T N_nu^-1 (d_nu - P_nu x) at mixing q."""
 
     @staticmethod
     def forward(ctx, x, q, model, *d):
-        maps = model.project(x.detach())
-        res = [t.detach() - m for t, m in zip(d, maps)]
-        val = sum(torch.dot(r, _tau(model, nu, x.device) * r) for nu, r in enumerate(res))
+        qd = q.detach()
+        with _Mixing(model, qd):
+            val, res = model.chi2(x.detach(), [t.detach() for t in d])
         ctx.model, ctx.qdev = model, q.device
-        ctx.save_for_backward(x.detach(), *res)
+        ctx.save_for_backward(qd, x.detach(), *res)
         return val
 
     @staticmethod
     def backward(ctx, g):
-        x, *res = ctx.saved_tensors
+        q, x, *res = ctx.saved_tensors
         model = ctx.model
-        # dChi2/dx = -2 sum P^T N^-1 r
-        grad_x = -2.0 * g * model.build_rhs(d=[r.unsqueeze(0) for r in res])[0]
-        grad_q = (g * db_dmix(model, -2.0 * x, res)).to(ctx.qdev)
-        grad_d = [2.0 * g * _tau(model, nu, x.device) * r for nu, r in enumerate(res)]
-        return grad_x, grad_q, None, *grad_d
+        with _Mixing(model, q):
+            # dChi2/dx = -2 sum P^T N^-1 r ; dChi2/dq = -2 x_k . [B Y^T N^-1 r] ; dChi2/dd = 2 N^-1 r
+            grad_x = g * model.build_rhs(d=[r.unsqueeze(0) for r in res])[0]
+            grad_q = db_dmix(model, x, res)
+            wres = model.noise_weight(res, scale=2.0)
+        return -2.0 * grad_x, (-2.0 * g * grad_q).to(ctx.qdev), None, *[g * w for w in wres]
 
 
 def mixing_matrix(freqs, comps, beta):

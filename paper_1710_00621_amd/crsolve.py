@@ -279,6 +279,57 @@ class Model:
                               _stream(dev)))
         return b
 
+    def _maps_arg(self, maps, keep):
+        """Host array of per-band device pointers (None entries stay NULL)."""
+        if maps is None:
+            return None
+        arr = (ctypes.c_void_p * self.nbands)()
+        for i, t in enumerate(maps):
+            if t is None:
+                arr[i] = None
+            else:
+                t = t.contiguous()
+                keep.append(t)
+                arr[i] = _dev_f64(t, "map")
+        return arr
+
+    def prior_quad(self, x):
+        """(1/2 x^T S^-1 x per right-hand side [nrhs], S^-1 x)."""
+        x2, sq = self._vec(x, "x")
+        y = torch.empty_like(x2)
+        val = torch.empty(x2.shape[0], dtype=torch.float64, device=x2.device)
+        check(lib().crs_prior_quad(self._h, x2.shape[0], _dev_f64(x2, "x"), _dev_f64(y, "y"),
+                                   _dev_f64(val, "val"), _stream(x2.device)))
+        return (val[0], y[0]) if sq else (val, y)
+
+    def chi2(self, x, d):
+        """(chi^2 = sum_nu (d - P x)^T N^-1 (d - P x) per right-hand side,
+        residual maps d - P x as a list of [nrhs, npix_nu] tensors).  d: per
+        band [nrhs, npix_nu] (or [npix_nu]) tensors, None = zero."""
+        x2, sq = self._vec(x, "x")
+        nrhs = x2.shape[0]
+        keep = []
+        dd = None if d is None else [None if t is None else (t.unsqueeze(0) if t.dim() == 1 else t)
+                                     for t in d]
+        res = [torch.empty((nrhs, g.npix), dtype=torch.float64, device=x2.device) for g in self.grids]
+        rarr = (ctypes.c_void_p * self.nbands)(*[r.data_ptr() for r in res])
+        val = torch.empty(nrhs, dtype=torch.float64, device=x2.device)
+        check(lib().crs_chi2(self._h, nrhs, _dev_f64(x2, "x"), self._maps_arg(dd, keep), rarr,
+                             _dev_f64(val, "val"), _stream(x2.device)))
+        return (val[0], [r[0] for r in res]) if sq else (val, res)
+
+    def noise_weight(self, maps, scale=1.0):
+        """scale N_nu^-1 maps_nu for every band (list of [nrhs, npix_nu] or [npix_nu])."""
+        keep = []
+        sq = maps[0].dim() == 1
+        mm = [t.unsqueeze(0) if t.dim() == 1 else t for t in maps]
+        nrhs = mm[0].shape[0]
+        out = [torch.empty((nrhs, g.npix), dtype=torch.float64, device=mm[0].device) for g in self.grids]
+        oarr = (ctypes.c_void_p * self.nbands)(*[o.data_ptr() for o in out])
+        check(lib().crs_noise_weight(self._h, nrhs, float(scale), self._maps_arg(mm, keep), oarr,
+                                     _stream(mm[0].device)))
+        return [o[0] for o in out] if sq else out
+
     def project(self, x):
         """P_nu x for every band: list of [nrhs, npix_nu] tensors."""
         x2, sq = self._vec(x, "x")
@@ -390,6 +441,14 @@ def kernel_stats(family):
     w = ctypes.c_double()
     check(lib().crs_kernel_stats(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
     return {"launches": n.value, "ms": ms.value, "work": w.value}
+
+
+def kernel_work_counts(family):
+    """Summed work of a kernel family three ways: float64-range triples
+    (the headline count), nominal triples, evaluated (>= 2^-100) triples."""
+    out = (ctypes.c_double * 3)()
+    check(lib().crs_kernel_work_counts(family.encode(), out))
+    return {"fp64": out[0], "nominal": out[1], "evaluated": out[2]}
 
 
 def kernel_stats_reset():

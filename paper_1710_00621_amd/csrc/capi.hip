@@ -18,8 +18,11 @@ bool g_prof_in_graphs = true;  // event records inside captured graphs
 struct ProfTotals {
   int64_t launches = 0;
   double ms = 0.0;
-  double work = 0.0;
+  Work3 work;
 };
+void add_work(Work3& a, const Work3& b) {
+  for (int i = 0; i < 3; ++i) a.w[i] += b.w[i];
+}
 ProfTotals g_prof_totals[FAM_COUNT];
 
 void prof_resolve_locked() {
@@ -28,7 +31,7 @@ void prof_resolve_locked() {
     if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
       g_prof_totals[r.family].launches += 1;
       g_prof_totals[r.family].ms += ms;
-      g_prof_totals[r.family].work += r.work;
+      add_work(g_prof_totals[r.family].work, r.work);
     } else {
       (void)hipGetLastError();
     }
@@ -67,7 +70,7 @@ bool record_event(hipEvent_t ev, hipStream_t s, bool captured) {
 }
 }  // namespace
 
-ProfScope::ProfScope(int fam, double w, hipStream_t st) : family(fam), work(w), s(st) {
+ProfScope::ProfScope(int fam, const Work3& w, hipStream_t st, int tg) : family(fam), work(w), tag(tg), s(st) {
   if (!g_prof_on) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) return;
@@ -95,10 +98,10 @@ ProfScope::~ProfScope() {
   }
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (captured) {
-    g_prof_captured.push_back({family, work, e0, e1});
+    g_prof_captured.push_back({family, work, tag, e0, e1});
     return;
   }
-  g_prof_pending.push_back({family, work, e0, e1});
+  g_prof_pending.push_back({family, work, tag, e0, e1});
   if (g_prof_pending.size() > 4096) prof_resolve_locked();
 }
 
@@ -119,7 +122,7 @@ std::vector<ProfRecord> prof_take_captured() {
   return out;
 }
 
-void prof_account(const std::vector<ProfRecord>& recs) {
+void prof_account(const std::vector<ProfRecord>& recs, const std::function<Work3(const ProfRecord&)>& work) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return;
   for (const auto& r : recs) {
@@ -127,7 +130,7 @@ void prof_account(const std::vector<ProfRecord>& recs) {
     if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
       g_prof_totals[r.family].launches += 1;
       g_prof_totals[r.family].ms += ms;
-      g_prof_totals[r.family].work += r.work;
+      add_work(g_prof_totals[r.family].work, work ? work(r) : r.work);
     } else {
       (void)hipGetLastError();  // keep a failed query from surfacing at a later launch check
     }
@@ -185,10 +188,22 @@ RingArgs ring_args(crs_grid g, int lmax) {
   return r;
 }
 
-double leg_flops(const ShtPlan& p, int nmaps) {
-  // per evaluated (ring pair, l, m): 4 flops of recurrence shared by the
-  // maps + 4 flops (cos and sin FMAs) per map
-  return (double)p.eff_triples * (4.0 + 4.0 * nmaps);
+Work3 leg_work(const ShtPlan& p, int nmaps) {
+  // per (ring pair, l, m): 4 flops of recurrence shared by the maps + 4 flops
+  // (cos and sin FMAs on the north / south combined sums) per map
+  Work3 w;
+  if (nmaps <= 0) return w;
+  const double per = 4.0 + 4.0 * nmaps;
+  w.w[0] = (double)p.fp64_triples * per;
+  w.w[1] = (double)p.nominal_triples * per;
+  w.w[2] = (double)p.eff_triples * per;
+  return w;
+}
+
+Work3 bytes_work(double bytes) {
+  Work3 w;
+  w.w[0] = w.w[1] = w.w[2] = bytes;
+  return w;
 }
 
 double ring_bytes(crs_grid g, int lmax, int nmaps, int mode) {
@@ -251,7 +266,22 @@ int crs_kernel_stats(const char* family, int64_t* launches, double* total_ms, do
     prof_resolve_locked();
     if (launches) *launches = g_prof_totals[f].launches;
     if (total_ms) *total_ms = g_prof_totals[f].ms;
-    if (total_work) *total_work = g_prof_totals[f].work;
+    if (total_work) *total_work = g_prof_totals[f].work.w[0];
+    return CRS_OK;
+  });
+}
+
+int crs_kernel_work_counts(const char* family, double* work3) {
+  return guarded([&] {
+    CRS_CHECK(family != nullptr && work3 != nullptr, CRS_EINVAL, "family or work3 is NULL");
+    int f = -1;
+    if (!std::strcmp(family, "legendre_synth")) f = FAM_LEG_SYNTH;
+    if (!std::strcmp(family, "legendre_adjoint")) f = FAM_LEG_ADJ;
+    if (!std::strcmp(family, "ring_fft")) f = FAM_RING;
+    CRS_CHECK(f >= 0, CRS_EINVAL, "unknown kernel family");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_resolve_locked();
+    for (int i = 0; i < 3; ++i) work3[i] = g_prof_totals[f].work.w[i];
     return CRS_OK;
   });
 }
@@ -279,11 +309,11 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
     w.phase.alloc((size_t)nmaps * pst);
     launch_tile_sum(p.hs.p, nalm, nmaps, alm, alm_stride, 1, 0, w.uhat.p, nalm, s);
     {
-      ProfScope ps(FAM_LEG_SYNTH, leg_flops(p, nmaps), s);
+      ProfScope ps(FAM_LEG_SYNTH, leg_work(p, nmaps), s);
       launch_leg_synth(leg_choice(p.npairs, lmax, nmaps), leg_args(g, p), nmaps, w.uhat.p, nalm, w.phase.p, pst, s);
     }
     {
-      ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_SYNTH), s);
+      ProfScope ps(FAM_RING, bytes_work(ring_bytes(g, lmax, nmaps, RING_SYNTH)), s);
       launch_ring(g, lmax, RING_SYNTH, nmaps, w.phase.p, pst, nullptr, map, map_stride,
                   nullptr, 1, s);
     }
@@ -308,12 +338,12 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
     w.phase.alloc((size_t)nmaps * pst);
     w.vpart.alloc((size_t)ntiles * nmaps * nalm);
     {
-      ProfScope ps(FAM_RING, ring_bytes(g, lmax, nmaps, RING_ADJOINT), s);
+      ProfScope ps(FAM_RING, bytes_work(ring_bytes(g, lmax, nmaps, RING_ADJOINT)), s);
       launch_ring(g, lmax, RING_ADJOINT, nmaps, w.phase.p, pst, map, nullptr, map_stride,
                   nullptr, 1, s);
     }
     {
-      ProfScope ps(FAM_LEG_ADJ, leg_flops(p, nmaps), s);
+      ProfScope ps(FAM_LEG_ADJ, leg_work(p, nmaps), s);
       launch_leg_adjoint(lc, leg_args(g, p), nmaps, w.phase.p, pst, w.vpart.p, nalm,
                          (int64_t)nmaps * nalm, false, s);
     }

@@ -436,6 +436,58 @@ __global__ void k_pix_rhs(double* __restrict__ f, const double* const* __restric
   }
 }
 
+// res[map] = d[map] - res[map] (res holds P x on entry; d NULL = zero) and
+// partial[map][blk] = this block's part of res^T tau res
+__global__ __launch_bounds__(256) void k_resid_chi2(double* const* __restrict__ res, const double* const* __restrict__ d,
+                                                    const double* const* __restrict__ tau, int64_t npix,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int map = blockIdx.y;
+  double* r = res[map];
+  const double* dv = d[map];
+  const double* t = tau[map];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)gridDim.x * 256) {
+    const double v = (dv ? dv[i] : 0.0) - r[i];
+    r[i] = v;
+    acc = fma(t[i] * v, v, acc);
+  }
+  const double sum = block_sum256(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)map * gridDim.x + blockIdx.x] = sum;
+}
+
+// out[map] = scale tau[map] in[map]
+__global__ void k_noise_weight(double* const* __restrict__ out, const double* const* __restrict__ in,
+                               const double* const* __restrict__ tau, double scale, int64_t npix) {
+  const int map = blockIdx.y;
+  double* o = out[map];
+  const double* v = in[map];
+  const double* t = tau[map];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)gridDim.x * 256)
+    o[i] = scale * t[i] * (v ? v[i] : 0.0);
+}
+
+// out[sys] = scale * sum of the partials of the system's maps: per system,
+// the ranges rng[j] (first, count) for j in [rofs[sys], rofs[sys + 1]), in order
+__global__ __launch_bounds__(256) void k_sum_ranges(const double* __restrict__ partial, const int2* __restrict__ rng,
+                                                    const int* __restrict__ rofs, double scale,
+                                                    double* __restrict__ out) {
+  const int sy = blockIdx.x;
+  double tot = 0.0;
+  for (int j = rofs[sy]; j < rofs[sy + 1]; ++j) {
+    const int2 r = rng[j];
+    tot += sum_partials(partial, r.x, r.y);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[sy] = scale * tot;
+}
+
+// out[sys] = scale * scal[sys][S_TMP]
+__global__ void k_scal_out(const double* __restrict__ scal, int nsys, double scale, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsys) out[i] = scale * scal[i * kScal + S_TMP];
+}
+
 inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
@@ -481,6 +533,7 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   }
   e->nsys = (int)e->hsys.size();
   e->ntot = off;
+  e->hact.assign(e->nsys, 1);
   // groups: maps (problem, band) x rhs, map = base + rhs
   std::map<std::pair<crs_grid, int>, int> gid;
   std::vector<std::vector<int>> bmap(np);  // per problem per band: map base
@@ -618,10 +671,39 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   return e;
 }
 
+namespace {
+// maps of group g whose system is active (all of them when not masked)
+int active_maps(const Exec& e, const ExecGroup& g, bool masked) {
+  if (!masked) return g.nmaps;
+  int n = 0;
+  for (const SlotDev& sl : g.hslots) n += e.hact[sl.sys] ? 1 : 0;
+  return n;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+}  // namespace
+
+// Algorithmic work of one operator launch of group gi over its active maps.
+Work3 group_work(const Exec& e, int gi, int family, bool masked) {
+  const ExecGroup& g = e.groups[gi];
+  const int na = active_maps(e, g, masked);
+  if (family == FAM_RING)
+    return bytes_work(na * (ring_bytes(g.grid, g.lmax, 1, RING_ROUNDTRIP) + (double)g.grid->npix * 8.0));
+  return leg_work(*g.plan, na);
+}
+
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act) {
   const bool pinv = kind == OP_PI;
   const bool skip_done = act != nullptr;
-  for (auto& g : e.groups) {
+  const bool cap = capturing(s);
+  for (int gi = 0; gi < (int)e.groups.size(); ++gi) {
+    ExecGroup& g = e.groups[gi];
+    // outside a capture, groups whose systems have all finished launch nothing
+    // (their partial sums are read only for active systems)
+    if (skip_done && !cap && active_maps(e, g, true) == 0) continue;
     MapSkip skip;
     if (skip_done) {
       skip.mapsys = g.mapsys.p;
@@ -634,17 +716,16 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
     {
-      ProfScope ps(FAM_LEG_SYNTH, leg_flops(*g.plan, g.nmaps), s);
+      ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done), s, gi);
       launch_leg_synth(g.leg, la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
     }
     {
-      ProfScope ps(FAM_RING, ring_bytes(g.grid, g.lmax, g.nmaps, RING_ROUNDTRIP) + (double)g.nmaps * g.grid->npix * 8.0,
-                   s);
+      ProfScope ps(FAM_RING, group_work(e, gi, FAM_RING, skip_done), s, gi);
       launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, g.nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
                   pinv ? g.wP.p : g.wA.p, 1, s, skip);
     }
     {
-      ProfScope ps(FAM_LEG_ADJ, leg_flops(*g.plan, g.nmaps), s);
+      ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done), s, gi);
       launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
                          s);
     }
@@ -669,9 +750,14 @@ void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double*
 
 void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,
                     const std::vector<std::vector<const double*>>& w1, hipStream_t s) {
+  std::vector<std::vector<const double*>> hold;  // alive until the sync below
+  hold.reserve(2 * e.groups.size());             // (references into it stay valid)
   for (auto& g : e.groups) {
     const int64_t npix = g.grid->npix;
-    std::vector<const double*> dp(g.nmaps), wp(g.nmaps);
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& dp = hold.back();
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& wp = hold.back();
     for (int i = 0; i < g.nmaps; ++i) {
       const SlotDev& sl = g.hslots[i];
       dp[i] = d.empty() ? nullptr : d[sl.sys][sl.band];
@@ -731,6 +817,89 @@ void exec_project(Exec& e, const double* x, const std::vector<std::vector<double
                              hipMemcpyDeviceToDevice, s));
     }
   }
+}
+
+// val[sys] = 1/2 x^T S^-1 x, y = S^-1 x
+void exec_prior_quad(Exec& e, const double* x, double* y, double* val, hipStream_t s) {
+  exec_prior_inv(e, x, y, s);
+  hipLaunchKernelGGL(k_dot, vgrid(e.nsys), dim3(256), 0, s, x, y, e.dsys.p, e.partial.p, (const double*)nullptr);
+  hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 4, e.partial.p, kDotBlocks, e.scal.p);
+  hipLaunchKernelGGL(k_scal_out, dim3((e.nsys + 255) / 256), dim3(256), 0, s, e.scal.p, e.nsys, 0.5, val);
+  CRS_HIP(hipGetLastError());
+}
+
+// res[sys][band] = d - P x (maps of the caller), val[sys] = sum_band res^T tau res
+void exec_chi2(Exec& e, const double* x, const std::vector<std::vector<const double*>>& d,
+               const std::vector<std::vector<double*>>& res, double* val, hipStream_t s) {
+  exec_project(e, x, res, s);
+  // per (system, band) map: kDotBlocks partials, grouped by band group
+  std::vector<int2> rng;
+  std::vector<std::vector<int2>> per(e.nsys);
+  int64_t base = 0;
+  // host pointer tables stay alive until the stream sync below
+  std::vector<std::vector<const double*>> hold;
+  hold.reserve(2 * e.groups.size());  // (references into it stay valid)
+  for (auto& g : e.groups) {
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& dp = hold.back();
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& rp = hold.back();
+    for (int i = 0; i < g.nmaps; ++i) {
+      const SlotDev& sl = g.hslots[i];
+      dp[i] = d.empty() ? nullptr : d[sl.sys][sl.band];
+      rp[i] = res[sl.sys][sl.band];
+      per[sl.sys].push_back(make_int2((int)(base + (int64_t)i * kDotBlocks), kDotBlocks));
+    }
+    g.dptr.upload(dp, s);
+    g.wptr.upload(rp, s);  // the residual maps (written in place)
+    base += (int64_t)g.nmaps * kDotBlocks;
+  }
+  e.chi2part.alloc((size_t)base);
+  std::vector<int> rofs(e.nsys + 1, 0);
+  for (int sy = 0; sy < e.nsys; ++sy) {
+    // bands in model order
+    rofs[sy + 1] = rofs[sy] + (int)per[sy].size();
+    for (auto& r : per[sy]) rng.push_back(r);
+  }
+  base = 0;
+  for (auto& g : e.groups) {
+    hipLaunchKernelGGL(k_resid_chi2, dim3(kDotBlocks, g.nmaps), dim3(256), 0, s, (double* const*)g.wptr.p,
+                       g.dptr.p, g.tau.p, g.grid->npix, e.chi2part.p + base);
+    CRS_HIP(hipGetLastError());
+    base += (int64_t)g.nmaps * kDotBlocks;
+  }
+  DevBuf<int2> drng;
+  DevBuf<int> drofs;
+  drng.upload(rng, s);
+  drofs.upload(rofs, s);
+  hipLaunchKernelGGL(k_sum_ranges, dim3(e.nsys), dim3(256), 0, s, e.chi2part.p, drng.p, drofs.p, 1.0, val);
+  CRS_HIP(hipGetLastError());
+  // the pointer tables are handle buffers; the range tables are temporaries
+  CRS_HIP(hipStreamSynchronize(s));
+}
+
+// out[sys][band] = scale tau_band in[sys][band] (in NULL = zero)
+void exec_noise_weight(Exec& e, double scale, const std::vector<std::vector<const double*>>& in,
+                       const std::vector<std::vector<double*>>& out, hipStream_t s) {
+  std::vector<std::vector<const double*>> hold;  // alive until the sync below
+  hold.reserve(2 * e.groups.size());             // (references into it stay valid)
+  for (auto& g : e.groups) {
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& ip = hold.back();
+    hold.emplace_back(g.nmaps);
+    std::vector<const double*>& op = hold.back();
+    for (int i = 0; i < g.nmaps; ++i) {
+      const SlotDev& sl = g.hslots[i];
+      ip[i] = in.empty() ? nullptr : in[sl.sys][sl.band];
+      op[i] = out[sl.sys][sl.band];
+    }
+    g.dptr.upload(ip, s);
+    g.wptr.upload(op, s);
+    hipLaunchKernelGGL(k_noise_weight, dim3(kDotBlocks, g.nmaps), dim3(256), 0, s, (double* const*)g.wptr.p,
+                       g.dptr.p, g.tau.p, scale, g.grid->npix);
+    CRS_HIP(hipGetLastError());
+  }
+  CRS_HIP(hipStreamSynchronize(s));
 }
 
 namespace {
@@ -888,9 +1057,13 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       if (active[i]) return true;
     return false;
   };
+  auto mirror = [&](const std::vector<int>& flags) {
+    for (int i = 0; i < ns; ++i) e.hact[i] = flags[i] ? 1 : 0;
+  };
   int it = 0;
   while (any_active() && it < maxiter) {
     ++it;
+    mirror(active);
     if (use_graph) {
       CRS_HIP(hipGraphLaunch(it == 1 ? e.graph_first : e.graph_iter, s));
     } else {
@@ -899,7 +1072,9 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
     }
     CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
     CRS_HIP(hipStreamSynchronize(s));
-    if (use_graph && prof) prof_account(it == 1 ? e.prof_first : e.prof_iter);
+    if (use_graph && prof)
+      prof_account(it == 1 ? e.prof_first : e.prof_iter,
+                   [&](const ProfRecord& r) { return r.tag >= 0 ? group_work(e, r.tag, r.family, true) : r.work; });
     bool cand = false;
     for (int i = 0; i < ns; ++i) {
       sel[i] = 0;
@@ -929,6 +1104,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       std::vector<double> cflag((size_t)ns * kScal, 0.0);  // lives past the sync that ends this block
       for (int i = 0; i < ns; ++i) cflag[(size_t)i * kScal] = sel[i] ? 1.0 : 0.0;
       CRS_HIP(hipMemcpyAsync(e.cand.p, cflag.data(), hsb, hipMemcpyHostToDevice, s));
+      mirror(sel);
       exec_apply(e, OP_A, e.xw.p, e.q.p, s, e.cand.p);
       hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
       dot_to(e, e.t.p, e.t.p, 4, s);

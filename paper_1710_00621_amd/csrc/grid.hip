@@ -382,7 +382,7 @@ __global__ void k_start_table(const double* __restrict__ gtab, const double* __r
                               const double* __restrict__ zp, const double* __restrict__ sp,
                               const double* __restrict__ pm_mant, const int* __restrict__ pm_exp,
                               int L, int npairs, double thr, int* __restrict__ ls_out,
-                              double2* __restrict__ ms_out) {
+                              double2* __restrict__ ms_out, double thr_lo, int* __restrict__ lu_out) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   int m = blockIdx.y;
   if (p >= npairs || m > L) return;
@@ -423,11 +423,13 @@ __global__ void k_start_table(const double* __restrict__ gtab, const double* __r
   const double* f = ftab + tri_off(L, m) - m;
   double mu_prev = 0.0, mu_cur = mant;
   int l = m;
-  int lsv = L + 1;
+  int lsv = L + 1, luv = L + 1;
   double2 msv = make_double2(0.0, 0.0);
-  // threshold test on |lambda_l| = f_l |mu_l| 2^e
+  // threshold tests on |lambda_l| = f_l |mu_l| 2^e: the first l at or above
+  // thr_lo (counted, not used by the kernels) and at or above thr (start)
   while (true) {
     double v = fabs(f[l] * mu_cur);
+    if (luv > L && v != 0.0 && e > -2000 && ldexp(v, (int)e) >= thr_lo) luv = l;
     if (v != 0.0 && e > -2000 && ldexp(v, (int)e) >= thr) {
       lsv = l;
       msv = make_double2(ldexp(mu_prev, (int)e), ldexp(mu_cur, (int)e));
@@ -446,9 +448,11 @@ __global__ void k_start_table(const double* __restrict__ gtab, const double* __r
   }
   ls_out[(size_t)m * npairs + p] = lsv;
   ms_out[(size_t)m * npairs + p] = msv;
+  lu_out[(size_t)m * npairs + p] = luv;
 }
 
 constexpr double kSkipThreshold = 0x1p-100;  // |lambda| below this is not evaluated
+constexpr double kFp64Normal = 0x1p-1022;    // smallest normal float64
 
 ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s) {
   auto it = g->plans.find(lmax);
@@ -513,21 +517,24 @@ ShtPlan& get_plan(crs_grid g, int lmax, hipStream_t s) {
   dpe.upload(pme, s);
   plan->ls.alloc((size_t)(L + 1) * plan->npairs);
   plan->ms.alloc((size_t)(L + 1) * plan->npairs);
+  DevBuf<int> dlu;
+  dlu.alloc((size_t)(L + 1) * plan->npairs);
   dim3 grid((plan->npairs + 127) / 128, L + 1);
   hipLaunchKernelGGL(k_start_table, grid, dim3(128), 0, s, plan->g.p, plan->f.p, g->d_zpair.p,
                      g->d_spair.p, dpm.p, dpe.p, L, plan->npairs, kSkipThreshold, plan->ls.p,
-                     plan->ms.p);
+                     plan->ms.p, kFp64Normal, dlu.p);
   CRS_HIP(hipGetLastError());
-  std::vector<int> lsh((size_t)(L + 1) * plan->npairs);
+  std::vector<int> lsh((size_t)(L + 1) * plan->npairs), luh(lsh.size());
   CRS_HIP(hipMemcpyAsync(lsh.data(), plan->ls.p, lsh.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  CRS_HIP(hipMemcpyAsync(luh.data(), dlu.p, luh.size() * sizeof(int), hipMemcpyDeviceToHost, s));
   CRS_HIP(hipStreamSynchronize(s));
-  int64_t eff = 0;
-  for (int m = 0; m <= L; ++m)
-    for (int p = 0; p < plan->npairs; ++p) {
-      int v = lsh[(size_t)m * plan->npairs + p];
-      if (v <= L) eff += L - v + 1;
-    }
+  int64_t eff = 0, eff64 = 0;
+  for (size_t i = 0; i < lsh.size(); ++i) {
+    if (lsh[i] <= L) eff += L - lsh[i] + 1;
+    if (luh[i] <= L) eff64 += L - luh[i] + 1;
+  }
   plan->eff_triples = eff;
+  plan->fp64_triples = eff64;
   plan->nominal_triples = (int64_t)plan->npairs * ntri;
   auto& ref = *plan;
   g->plans[lmax] = std::move(plan);

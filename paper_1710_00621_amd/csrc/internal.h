@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -102,7 +103,8 @@ constexpr int kBlueMax = 8192;   // longest Bluestein convolution (power of two)
 struct ShtPlan {
   int lmax = 0;
   int npairs = 0;
-  int64_t eff_triples = 0;     // (ring pair, l, m) triples the kernels evaluate
+  int64_t eff_triples = 0;     // (ring pair, l, m) triples the kernels evaluate (|lambda| >= 2^-100)
+  int64_t fp64_triples = 0;    // triples whose |lambda| reaches the float64 normal range
   int64_t nominal_triples = 0; // npairs * (L+1)(L+2)/2
   DevBuf<double> g;            // triangle: g_lm, mu recurrence coefficient
   DevBuf<double> f;            // triangle: f_lm, lambda = f * mu
@@ -260,25 +262,40 @@ void launch_hat_scale(const double* f, int lmax, int nmaps, const double* in, in
 // captured into a graph the event records become graph nodes; the pairs are
 // then handed to the graph's owner (prof_take_captured), which accounts them
 // after every replay (prof_account) and frees them (prof_release).
+// Work of a launch, three ways: the Legendre flops counted over the (ring
+// pair, l, m) triples whose |lambda| reaches the float64 normal range (w[0],
+// the headline count), over all triples (w[1], nominal) and over the triples
+// the kernels evaluate (w[2], |lambda| >= 2^-100); ring launches carry their
+// algorithmic bytes in all three.
+struct Work3 {
+  double w[3] = {0.0, 0.0, 0.0};
+};
 struct ProfRecord {
   int family;
-  double work;
+  Work3 work;
+  int tag;  // owner's label (a group index) for replay-time work, -1: fixed
   hipEvent_t e0, e1;
 };
 struct ProfScope {
   int family;
-  double work;
+  Work3 work;
+  int tag;
   hipStream_t s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool captured = false;
-  ProfScope(int fam, double w, hipStream_t st);
+  ProfScope(int fam, const Work3& w, hipStream_t st, int tag = -1);
   ~ProfScope();
 };
 enum { FAM_LEG_SYNTH = 0, FAM_LEG_ADJ = 1, FAM_RING = 2, FAM_COUNT = 3 };
 bool prof_enabled();
 void prof_disable_in_graphs();  // if a graph cannot hold event records
 std::vector<ProfRecord> prof_take_captured();
-void prof_account(const std::vector<ProfRecord>& recs);
+// Accounts one replay; work (optional) gives each record's work for this
+// replay (records of finished systems' maps do less), else the recorded work.
+void prof_account(const std::vector<ProfRecord>& recs,
+                  const std::function<Work3(const ProfRecord&)>& work = nullptr);
 void prof_release(std::vector<ProfRecord>& recs);
+Work3 leg_work(const ShtPlan& p, int nmaps);
+Work3 bytes_work(double bytes);
 
 }  // namespace crs

@@ -1062,6 +1062,8 @@ LegChoice leg_autotune(const LegArgs& a0, int nmaps, double* uhat, double2* phas
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(a.npairs, L, nmaps)] = best;
   }
+  // the environment overrides apply to a tuned choice as to the default one
+  apply_env(best, nmaps);
   return best;
 }
 

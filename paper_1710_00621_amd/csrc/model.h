@@ -9,7 +9,6 @@ namespace crs {
 
 LegArgs leg_args(crs_grid g, ShtPlan& p);
 RingArgs ring_args(crs_grid g, int lmax);
-double leg_flops(const ShtPlan& p, int nmaps);
 double ring_bytes(crs_grid g, int lmax, int nmaps, int mode);
 
 __host__ __device__ inline int64_t moff_h(int L, int m) {
@@ -119,9 +118,13 @@ struct Exec {
   int nwl_sys = 0;
   DevBuf<int2> rng_sys;           // per system: (first block, block count) in wl_sys
   DevBuf<double> wpart;           // per work-list block partial dot products
+  DevBuf<double> chi2part;        // per (system, band) partial sums of the chi-square
   std::vector<DevBuf<const double*>> vptr;
   std::vector<DevBuf<int>> binfo;
   bool has_diag = true;
+  // host mirror of the activity flags handed to the operators (act): which
+  // systems' maps do work; credits profiled launches with that work only
+  std::vector<char> hact;
   // PCG workspace
   DevBuf<double> r, z, p, q, t, partial, scal, cand;
   DevBuf<int> dsel;
@@ -154,6 +157,9 @@ void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t
 // wpart (optional): per block of the system work list, its part of r . z
 void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act = nullptr,
                double* wpart = nullptr);
+// algorithmic work of one launch of group gi (family FAM_*) over the maps
+// whose system is active in e.hact (masked) or over all of them
+Work3 group_work(const Exec& e, int gi, int family, bool masked);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
@@ -169,6 +175,14 @@ void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
               hipStream_t s);
 // maps[sys][band] <- P_band x_sys
 void exec_project(Exec& e, const double* x, const std::vector<std::vector<double*>>& maps, hipStream_t s);
+// y = S^-1 x and val[sys] = 1/2 x^T S^-1 x (val: device, one per system)
+void exec_prior_quad(Exec& e, const double* x, double* y, double* val, hipStream_t s);
+// res[sys][band] = d - P x and val[sys] = sum_band res^T N^-1 res (device)
+void exec_chi2(Exec& e, const double* x, const std::vector<std::vector<const double*>>& d,
+               const std::vector<std::vector<double*>>& res, double* val, hipStream_t s);
+// out[sys][band] = scale N^-1_band in[sys][band]
+void exec_noise_weight(Exec& e, double scale, const std::vector<std::vector<const double*>>& in,
+                       const std::vector<std::vector<double*>>& out, hipStream_t s);
 // PCG on every system of e.  b, x stacked.  use_graph: run each iteration as
 // one captured hipGraph.
 int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,

@@ -544,6 +544,47 @@ int apply_db_dmix(crs_model m, int nrhs, const double* lam, const double* const*
   });
 }
 
+int crs_prior_quad(crs_model m, int nrhs, const double* x, double* y, double* val, crs_stream st) {
+  return guarded([&] {
+    check_vec(m, nrhs, x, y);
+    CRS_CHECK(val != nullptr, CRS_EINVAL, "val is NULL");
+    hipStream_t s = (hipStream_t)st;
+    exec_prior_quad(model_exec(m, nrhs, s), x, y, val, s);
+    return CRS_OK;
+  });
+}
+
+int crs_chi2(crs_model m, int nrhs, const double* x, const double* const* d, double* const* res, double* val,
+             crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(m != nullptr && x != nullptr && res != nullptr && val != nullptr, CRS_EINVAL,
+              "model, x, res or val is NULL");
+    CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
+    for (int nu = 0; nu < m->nbands; ++nu) CRS_CHECK(res[nu] != nullptr, CRS_EINVAL, "res entry is NULL");
+    hipStream_t s = (hipStream_t)st;
+    std::vector<std::vector<double*>> rp(nrhs, std::vector<double*>(m->nbands));
+    for (int r = 0; r < nrhs; ++r)
+      for (int nu = 0; nu < m->nbands; ++nu) rp[r][nu] = res[nu] + (int64_t)r * m->bands[nu].npix;
+    exec_chi2(model_exec(m, nrhs, s), x, sys_band_ptrs(m, nrhs, d), rp, val, s);
+    return CRS_OK;
+  });
+}
+
+int crs_noise_weight(crs_model m, int nrhs, double scale, const double* const* in, double* const* out,
+                     crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(m != nullptr && out != nullptr, CRS_EINVAL, "model or out is NULL");
+    CRS_CHECK(nrhs >= 1, CRS_EINVAL, "nrhs must be >= 1");
+    for (int nu = 0; nu < m->nbands; ++nu) CRS_CHECK(out[nu] != nullptr, CRS_EINVAL, "out entry is NULL");
+    hipStream_t s = (hipStream_t)st;
+    std::vector<std::vector<double*>> op(nrhs, std::vector<double*>(m->nbands));
+    for (int r = 0; r < nrhs; ++r)
+      for (int nu = 0; nu < m->nbands; ++nu) op[r][nu] = out[nu] + (int64_t)r * m->bands[nu].npix;
+    exec_noise_weight(model_exec(m, nrhs, s), scale, sys_band_ptrs(m, nrhs, in), op, s);
+    return CRS_OK;
+  });
+}
+
 int crs_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs, int64_t n, double* out, crs_stream st) {
   return guarded([&] {
     CRS_CHECK(out != nullptr && n >= 0, CRS_EINVAL, "out is NULL or n < 0");

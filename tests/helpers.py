@@ -58,3 +58,10 @@ def small_model(ncomp=2, seed=0, mask=False, grids=(("healpix", 4), ("healpix", 
         comps.append({"lmax": L, "invcl": inputs.inv_cl(kinds[k], L, amplitude=0.05)})
     q = np.abs(rng.normal(1.0, 0.5, (len(bands), ncomp))) + 0.2
     return Model(bands, comps, q)
+
+
+def rel_max(a, b):
+    """max |a - b| / max |b|: an element-wise comparison on the scale of b."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -45,6 +45,62 @@ def _loss(beta, d):
     return gradient.wf_loss_and_gradient(mdl, d, _solver(mdl))
 
 
+def test_power_law_sed_closed_forms():
+    """(nu / nu_ref)^beta: 1 at the reference frequency, exact powers of two
+    at octaves."""
+    assert gradient.sed_value("sync", 30.0, -3.0, 30.0) == 1.0
+    assert gradient.sed_value("sync", 60.0, -3.0, 30.0) == 0.125
+    assert gradient.sed_value("sync", 15.0, -3.0, 30.0) == 8.0
+    assert gradient.sed_value("cmb", 857.0, 0.0, 1.0) == 1.0
+
+
+def _mbb_rj_planck(freq_ghz, beta, nu_ref_ghz, temp):
+    """Modified black body nu^beta B_nu(T) converted to Rayleigh-Jeans
+    brightness temperature (T_RJ = c^2 I / (2 k nu^2)), normalised at nu_ref,
+    from the Planck function in SI units with the exact SI values of h and k
+    (a different route to the same quantity as sed_value)."""
+    import mpmath as mp
+    h = mp.mpf("6.62607015e-34")
+    k = mp.mpf("1.380649e-23")
+
+    def t_rj(nu_hz):
+        planck = nu_hz ** 3 / (mp.exp(h * nu_hz / (k * temp)) - 1)  # 2 h / c^2 cancels
+        return nu_hz ** beta * planck / nu_hz ** 2
+    return t_rj(mp.mpf(freq_ghz) * 10 ** 9) / t_rj(mp.mpf(nu_ref_ghz) * 10 ** 9)
+
+
+def test_dust_sed_matches_planck_function():
+    """The dust mixing scalar against the Planck-function definition (h / k in
+    the oracle is the SI ratio rounded to 7 digits: relative agreement 1e-7).
+    A wrong reference frequency, exponent (beta vs beta + 1) or h / k scale
+    fails this."""
+    import mpmath as mp
+    for f in (30.0, 44.0, 143.0, 353.0, 545.0, 857.0):
+        for beta, temp in ((1.6, 20.0), (1.2, 15.0), (2.0, 25.0)):
+            with mp.workdps(40):
+                ref = float(_mbb_rj_planck(f, beta, 353.0, temp))
+            got = gradient.sed_value("dust", f, beta, 353.0, temp)
+            assert abs(got - ref) <= 1e-7 * abs(ref), (f, beta, temp, got, ref)
+    assert gradient.sed_value("dust", 353.0, 1.6, 353.0) == 1.0
+
+
+def test_sed_beta_derivative_matches_high_precision_derivative():
+    """d q / d beta against a 40-digit numerical derivative of the Planck-
+    function form (mpmath), independent of sed_dbeta's closed form."""
+    import mpmath as mp
+    for f in (30.0, 100.0, 353.0, 857.0):
+        for beta in (1.6, 1.3):
+            with mp.workdps(40):
+                ref = float(mp.diff(lambda b: _mbb_rj_planck(f, b, 353.0, 20.0), mp.mpf(beta)))
+            got = gradient.sed_dbeta("dust", f, beta, 353.0, 20.0)
+            assert abs(got - ref) <= 1e-7 * max(abs(ref), 1e-12), (f, beta, got, ref)
+        for beta in (-3.0, -2.5):
+            with mp.workdps(40):
+                ref = float(mp.diff(lambda b: (mp.mpf(f) / 30) ** b, mp.mpf(beta)))
+            got = gradient.sed_dbeta("sync", f, beta, 30.0)
+            assert abs(got - ref) <= 1e-13 * max(abs(ref), 1e-12), (f, beta, got, ref)
+
+
 def test_sed_derivative_matches_finite_difference():
     for kind, beta, ref in KINDS[1:]:
         for f in FREQS:

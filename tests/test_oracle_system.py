@@ -222,3 +222,31 @@ def test_normals_statistics():
     x = philox.normals(7, 0x100, 0, 200000)
     assert abs(x.mean()) < 0.01 and abs(x.var() - 1) < 0.01
     assert abs(np.mean(x ** 4) - 3) < 0.05
+
+
+def test_uniform_words_closed_forms():
+    """((w >> 11) + 0.5) 2^-53 at the ends of the 64-bit range and one step in."""
+    u = philox.uniforms(np.array([0, 2 ** 64 - 1, 2 ** 11, 2 ** 63], dtype=np.uint64))
+    assert u[0] == 2.0 ** -54
+    assert u[1] == 1.0 - 2.0 ** -54
+    assert u[2] == 1.5 * 2.0 ** -53
+    assert u[3] == 0.5 + 2.0 ** -54
+
+
+def test_box_muller_closed_forms():
+    """Box and Muller (1958): X1 = sqrt(-2 ln U1) cos(2 pi U2), X2 = sqrt(-2 ln U1)
+    sin(2 pi U2), evaluated at inputs whose outputs are known in closed form.
+    Swapping cos and sin, or the roles of the two uniforms of a pair, or the
+    pairing (u0, u1), (u2, u3), changes at least one of these values."""
+    e2, eh = math.exp(-2.0), math.exp(-0.5)
+    u = np.array([[e2, 1.0 / 12.0, eh, 0.25],
+                  [e2, 0.5, eh, 0.125]])
+    z = philox.box_muller(u)
+    # radius sqrt(-2 ln e^-2) = 2 at angle pi/6; radius 1 at angle pi/2
+    np.testing.assert_allclose(z[0], [math.sqrt(3.0), 1.0, 0.0, 1.0], atol=2e-15)
+    # radius 2 at angle pi; radius 1 at angle pi/4
+    np.testing.assert_allclose(z[1], [-2.0, 0.0, math.sqrt(0.5), math.sqrt(0.5)], atol=2e-15)
+    # normals() is uniforms() then box_muller() on blocks of four words
+    w = philox.raw_words(5, 0x101, 3, 8)
+    ref = philox.box_muller(philox.uniforms(w).reshape(2, 4)).reshape(-1)
+    np.testing.assert_array_equal(philox.normals(5, 0x101, 3, 8), ref)
