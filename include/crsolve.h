@@ -104,6 +104,24 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
 int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride,
                 double* alm, int64_t alm_stride, crs_stream s);
 
+/* sht_adjoint_noalloc: sht_adjoint for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and result as sht_adjoint, but
+ * its scratch (the phase array and the per-tile partial sums) lives in one
+ * static device array of 64 MiB that the library holds on every GPU it runs
+ * on until the process ends; the call itself allocates nothing.
+ * Preconditions: the (grid, lmax) Legendre tables already exist (created by
+ * any earlier sht_synth / sht_adjoint on that pair, or by a model using it);
+ * otherwise CRS_EINVAL.  A request whose scratch exceeds 64 MiB (e.g. more
+ * than about two maps at HEALPix Nside 256 / lmax 512) returns CRS_EINVAL
+ * with the needed size in the message.  All calls on one GPU share that
+ * GPU's array: calls that overlap in time on one GPU (different streams or
+ * threads) race and must be serialised by the caller.  Nothing in the array
+ * needs clearing between calls: every scratch entry is written before it is
+ * read. */
+int sht_adjoint_noalloc(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride,
+                        double* alm, int64_t alm_stride, crs_stream s);
+
 /*
  * Legendre kernel autotuning (the recurrence and contraction of Sect. 2.1,
  * the bulk of every transform).  Both transforms have several kernel

@@ -60,6 +60,8 @@ _SIGS = {
                                  ctypes.c_int64, vp]),
     "sht_adjoint": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp,
                                    ctypes.c_int64, vp]),
+    "sht_adjoint_noalloc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp,
+                                           ctypes.c_int64, vp]),
     "crs_autotune_legendre": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp]),
     "crs_legendre_choice": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "crs_model_create": (ctypes.c_int, [ctypes.POINTER(ModelDesc), vp, ctypes.POINTER(vp)]),

@@ -352,6 +352,82 @@ int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_
   });
 }
 
+}  // extern "C"
+
+namespace {
+// Scratch of sht_adjoint_noalloc: the phase array and the adjoint's per-tile
+// partial sums, in one static device array (each GPU holds its own copy until
+// the process ends).  Host code never passes the array's name to a kernel or
+// a copy: it uses the device address looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on
+// that device, with the device current).
+void* scratch_address() {
+  int dev = 0;
+  CRS_HIP(hipGetDevice(&dev));
+  CRS_CHECK(dev >= 0 && dev < kMaxDevices, CRS_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CRS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CRS_CHECK(p != nullptr, CRS_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+}  // namespace
+
+extern "C" {
+
+int sht_adjoint_noalloc(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride, double* alm,
+                        int64_t alm_stride, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(alm != nullptr && map != nullptr, CRS_EINVAL, "alm or map is NULL");
+    check_maps(lmax, nmaps, alm_stride, map_stride, g->npix);
+    hipStream_t s = (hipStream_t)st;
+    auto it = g->plans.find(lmax);
+    CRS_CHECK(it != g->plans.end(), CRS_EINVAL,
+              "no Legendre tables for this (grid, lmax) yet: create them with one sht_synth or "
+              "sht_adjoint call (or a model using the pair) before calling sht_adjoint_noalloc");
+    ShtPlan& p = *it->second;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
+    const int64_t pst = (int64_t)g->nring * (lmax + 1);
+    const LegChoice lc = leg_choice(p.npairs, lmax, nmaps);
+    const int ntiles = leg_adjoint_tiles(lc, p.npairs, false);
+    const size_t phase_bytes = align256((size_t)nmaps * pst * sizeof(double2));
+    const size_t part_bytes = align256((size_t)ntiles * nmaps * nalm * sizeof(double));
+    CRS_CHECK(phase_bytes + part_bytes <= kNoAllocScratchBytes, CRS_EINVAL,
+              "sht_adjoint_noalloc needs " + std::to_string(phase_bytes + part_bytes) +
+                  " bytes of scratch for this (grid, lmax, nmaps); its limit is " +
+                  std::to_string(kNoAllocScratchBytes) + " bytes (use sht_adjoint)");
+    unsigned char* base = static_cast<unsigned char*>(scratch_address());
+    double2* phase = reinterpret_cast<double2*>(base);
+    double* vpart = reinterpret_cast<double*>(base + phase_bytes);
+    // every entry of both scratch regions is written before it is read: the
+    // ring stage writes all m <= lmax of every ring and map, and every tile of
+    // the Legendre adjoint writes its whole partial vector
+    {
+      ProfScope ps(FAM_RING, bytes_work(ring_bytes(g, lmax, nmaps, RING_ADJOINT)), s);
+      launch_ring(g, lmax, RING_ADJOINT, nmaps, phase, pst, map, nullptr, map_stride, nullptr, 1, s);
+    }
+    {
+      ProfScope ps(FAM_LEG_ADJ, leg_work(p, nmaps), s);
+      launch_leg_adjoint(lc, leg_args(g, p), nmaps, phase, pst, vpart, nalm, (int64_t)nmaps * nalm, false, s);
+    }
+    launch_tile_sum(p.hs.p, nalm, nmaps, vpart, nalm, ntiles, (int64_t)nmaps * nalm, alm, alm_stride, s);
+    return CRS_OK;
+  });
+}
+
 int crs_autotune_legendre(crs_grid g, int lmax, int nmaps, crs_stream st) {
   return guarded([&] {
     CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
