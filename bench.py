@@ -377,8 +377,11 @@ def main():
         per_rhs = ms_per_step / nrhs
         roof = _roofline(crsolve, ms_per_step * a.steps, a.workload)
         log(f"batched: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
-        mode = (f"batched: one stacked PCG over all {nrhs} problems, each iteration one captured "
-                f"hipGraph")
+        gstats = batch.stats()
+        extra["graphs"] = {**gstats, "iterations_per_launch": gstats["iterations"] / max(1, gstats["graph_launches"])}
+        mode = (f"batched: one stacked PCG over all {nrhs} problems in chunks of 8 iterations per "
+                f"captured hipGraph launch (convergence tested on the device, the host reading flags "
+                f"between chunks; finished transform groups left out)")
         # Legendre kernel variant per (grid, L) group, as picked by the autotuner at batch creation
         groups = {}
         for p in probs:

@@ -288,12 +288,21 @@ int crs_batch_info(crs_batch b, int* nprob, int64_t* ntot);
  * each npix_nu doubles.  seeds: host array of nprob Philox seeds (CR mode;
  * problem p draws exactly the omegas of constrained_realization with seed
  * seeds[p]).  x: host array of nprob device pointers receiving n_p doubles.
- * iters, relres: host arrays of nprob, may be NULL.  use_graph != 0 runs each
- * PCG iteration as one captured hipGraph (captured on the first solve with a
- * given preconditioner and reused).  Returns as pcg_solve. */
+ * iters, relres: host arrays of nprob, may be NULL.  use_graph != 0 runs the
+ * PCG (Sect. 2.3) in chunks of 8 iterations, each chunk one captured hipGraph
+ * launch: every iteration stops the problems whose recursive residual passes
+ * rtol on the device, and between chunks the host checks their true
+ * residuals and restarts the ones that fail; transform groups whose problems
+ * have all finished are left out of the graph (graphs are captured per set of
+ * live groups and kept for later solves).  use_graph = 0 runs one iteration
+ * at a time with a host decision after each.  Returns as pcg_solve. */
 int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const uint64_t* seeds,
                     int precond, double rtol, int maxiter, double* const* x, int* iters,
                     double* relres, int use_graph, crs_stream s);
+/* Counters of the batch's last solve (host array out[4]): iterations of the
+ * slowest problem, graph launches, graphs captured, host reads of the PCG
+ * flags. */
+int crs_batch_stats(crs_batch b, int* out);
 
 /* ------------------------------------------------------------- profiling
  * With profiling on, every Legendre-stage kernel launch is bracketed by HIP

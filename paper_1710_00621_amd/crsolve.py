@@ -422,6 +422,13 @@ class Batch:
             check(st)
         return xs, {"status": st, "iters": list(iters), "relres": list(rel)}
 
+    def stats(self):
+        """Counters of the last solve: iterations, graph_launches,
+        graph_captures, host_syncs."""
+        out = (ctypes.c_int * 4)()
+        check(lib().crs_batch_stats(self._h, out))
+        return dict(zip(("iterations", "graph_launches", "graph_captures", "host_syncs"), list(out)))
+
 
 def philox_normals(seed, stream, rhs, n, device="cuda"):
     out = torch.empty(n, dtype=torch.float64, device=device)

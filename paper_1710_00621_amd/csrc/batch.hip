@@ -4,7 +4,8 @@
 // them: bands of all problems that share (grid, L) become the maps of one
 // group, so each Legendre / ring launch covers every problem at once, and the
 // PCG iteration (Sect. 2.3) advances every problem with its own scalars.
-// With use_graph each iteration is one captured hipGraph launch.  The
+// With use_graph the PCG runs in chunks of iterations, each chunk one captured
+// hipGraph launch that tests convergence on the device (exec_pcg).  The
 // constrained-realization right-hand side of problem p uses the Philox
 // streams of constrained_realization with seed p, so a batched solve matches
 // the per-model solves.
@@ -104,6 +105,18 @@ int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const 
                              s));
     CRS_HIP(hipStreamSynchronize(s));
     return rc;
+  });
+}
+
+int crs_batch_stats(crs_batch b, int* out) {
+  return guarded([&] {
+    CRS_CHECK(b != nullptr && out != nullptr, CRS_EINVAL, "batch or out is NULL");
+    const ExecStats& st = b->ex->stats;
+    out[0] = st.iterations;
+    out[1] = st.graph_launches;
+    out[2] = st.graph_captures;
+    out[3] = st.host_syncs;
+    return CRS_OK;
   });
 }
 

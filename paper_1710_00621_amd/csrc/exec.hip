@@ -507,13 +507,10 @@ void dot_to(Exec& e, const double* a, const double* b, int op, hipStream_t s, co
 }  // namespace
 
 Exec::~Exec() {
+  graphs.clear();
   if (hscal) (void)hipHostFree(hscal);
   if (hsel) (void)hipHostFree(hsel);
-  if (graph_first) (void)hipGraphExecDestroy(graph_first);
-  if (graph_iter) (void)hipGraphExecDestroy(graph_iter);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  prof_release(prof_first);
-  prof_release(prof_iter);
 }
 
 std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s, bool autotune) {
@@ -667,6 +664,10 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   CRS_HIP(hipHostMalloc((void**)&e->hscal, (size_t)e->nsys * kScal * sizeof(double), hipHostMallocDefault));
   CRS_HIP(hipHostMalloc((void**)&e->hsel, (size_t)e->nsys * sizeof(int), hipHostMallocDefault));
   e->dsel.alloc(e->nsys);
+  e->dcand.alloc(e->nsys);
+  e->bbdev.alloc(e->nsys);
+  e->hrows.alloc((size_t)kChunk * e->nsys);
+  e->live.assign(e->groups.size(), 1);
   CRS_HIP(hipStreamSynchronize(s));
   return e;
 }
@@ -701,9 +702,13 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
   const bool cap = capturing(s);
   for (int gi = 0; gi < (int)e.groups.size(); ++gi) {
     ExecGroup& g = e.groups[gi];
-    // outside a capture, groups whose systems have all finished launch nothing
-    // (their partial sums are read only for active systems)
+    // groups whose systems have all finished launch nothing (their partial
+    // sums are read only for active systems): outside a capture from the
+    // host's activity mirror, inside one from the live-group set it was
+    // captured for
     if (skip_done && !cap && active_maps(e, g, true) == 0) continue;
+    if (skip_done && cap && !e.live[gi]) continue;
+    const int tag = e.chunk_iter * 1024 + gi;
     MapSkip skip;
     if (skip_done) {
       skip.mapsys = g.mapsys.p;
@@ -716,16 +721,16 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
     {
-      ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done), s, gi);
+      ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done), s, tag);
       launch_leg_synth(g.leg, la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
     }
     {
-      ProfScope ps(FAM_RING, group_work(e, gi, FAM_RING, skip_done), s, gi);
+      ProfScope ps(FAM_RING, group_work(e, gi, FAM_RING, skip_done), s, tag);
       launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, g.nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
                   pinv ? g.wP.p : g.wA.p, 1, s, skip);
     }
     {
-      ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done), s, gi);
+      ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done), s, tag);
       launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
                          s);
     }
@@ -974,6 +979,48 @@ hipGraphExec_t capture(Exec& e, hipStream_t cs, const std::function<void()>& bod
 
 }  // namespace
 
+namespace {
+
+// Start of iteration j of a chunk: row[i] = 0 if system i is active, else -1.
+__global__ void k_chunk_start(const double* __restrict__ scal, double* __restrict__ row, int nsys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsys) row[i] = scal[i * kScal + S_ACTIVE] != 0.0 ? 0.0 : -1.0;
+}
+
+// End of iteration j of a chunk: row[i] = |r|^2 of a system that ran the
+// iteration (-2 if it broke down in it); a system whose recursive residual
+// passes rtol stops (inactive for the rest of the chunk) and becomes a
+// candidate for the host's true-residual check.
+__global__ void k_chunk_check(double* __restrict__ scal, const double* __restrict__ bb, double rtol2,
+                              double* __restrict__ row, double* __restrict__ cand, int nsys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsys || row[i] < 0.0) return;
+  double* st = scal + i * kScal;
+  if (st[S_ACTIVE] == 0.0) {
+    row[i] = -2.0;
+    return;
+  }
+  const double rr = st[S_RR];
+  if (!isfinite(rr)) {
+    st[S_BREAK] = 1.0;
+    st[S_ACTIVE] = 0.0;
+    row[i] = -2.0;
+    return;
+  }
+  row[i] = rr;
+  if (rr <= rtol2 * bb[i]) {
+    st[S_ACTIVE] = 0.0;
+    cand[i] = 1.0;
+  }
+}
+
+}  // namespace
+
+Exec::GraphEntry::~GraphEntry() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  prof_release(prof);
+}
+
 int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,
              double* relres, double* history, bool use_graph, hipStream_t s) {
   CRS_CHECK(precond == CRS_PRECOND_NONE || precond == CRS_PRECOND_DIAG || precond == CRS_PRECOND_PINV,
@@ -981,7 +1028,9 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   CRS_CHECK(precond != CRS_PRECOND_DIAG || e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
   CRS_CHECK(rtol > 0.0 && maxiter >= 0, CRS_EINVAL, "rtol must be > 0 and maxiter >= 0");
   const int ns = e.nsys;
+  const int ng = (int)e.groups.size();
   const size_t bytes = (size_t)e.ntot * sizeof(double);
+  e.stats = ExecStats{};
   // scalars and flags go through pinned host memory (plain DMA transfers)
   double* const hs = e.hscal;
   const size_t hsb = (size_t)ns * kScal * sizeof(double);
@@ -989,6 +1038,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   std::fill(hs, hs + (size_t)ns * kScal, 0.0);
   for (int i = 0; i < ns; ++i) hs[i * kScal + S_ACTIVE] = 1.0;
   CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
+  std::fill(e.live.begin(), e.live.end(), 1);
   // |b|^2
   dot_to(e, b, b, 4, s);
   CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
@@ -1016,42 +1066,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       active[i] = 0;
       status[i] = hs[i * kScal + S_BREAK] != 0.0 ? 2 : 0;  // r = 0 (x0 exact) counts as converged
     }
-  // graphs of the iteration body
   const bool prof = prof_enabled();
-  if (use_graph) {
-    const int key = precond * 2 + (prof ? 1 : 0);
-    if (e.graph_key != key) {
-      if (e.graph_first) (void)hipGraphExecDestroy(e.graph_first);
-      if (e.graph_iter) (void)hipGraphExecDestroy(e.graph_iter);
-      e.graph_first = e.graph_iter = nullptr;
-      prof_release(e.prof_first);
-      prof_release(e.prof_iter);
-      e.graph_key = -1;
-      if (!e.cap_stream) CRS_HIP(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
-      hipStream_t cs = e.cap_stream;
-      auto build = [&] {
-        e.graph_first = capture(e, cs, [&] { iter_apply(e, cs); }, e.prof_first);
-        e.graph_iter = capture(e, cs, [&] {
-          iter_precond(e, precond, cs);
-          iter_apply(e, cs);
-        }, e.prof_iter);
-      };
-      try {
-        build();
-      } catch (const Error&) {
-        if (!prof) throw;
-        // the runtime refused event records inside the capture: capture
-        // without them (kernel timing is then unavailable inside graphs)
-        (void)hipGetLastError();
-        if (e.graph_first) (void)hipGraphExecDestroy(e.graph_first);
-        e.graph_first = nullptr;
-        prof_release(e.prof_first);
-        prof_disable_in_graphs();
-        build();
-      }
-      e.graph_key = key;
-    }
-  }
   auto any_active = [&] {
     for (int i = 0; i < ns; ++i)
       if (active[i]) return true;
@@ -1060,82 +1075,188 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   auto mirror = [&](const std::vector<int>& flags) {
     for (int i = 0; i < ns; ++i) e.hact[i] = flags[i] ? 1 : 0;
   };
-  int it = 0;
-  while (any_active() && it < maxiter) {
-    ++it;
-    mirror(active);
-    if (use_graph) {
-      CRS_HIP(hipGraphLaunch(it == 1 ? e.graph_first : e.graph_iter, s));
-    } else {
-      if (it > 1) iter_precond(e, precond, s);
-      iter_apply(e, s);
-    }
+  // true residual of the systems sel marks: the ones within rtol finish, the
+  // others restart from their iterate (r = b - A x, beta = 0)
+  auto true_residual_check = [&] {
+    std::vector<double> cflag((size_t)ns * kScal, 0.0);  // lives past the sync that ends this block
+    for (int i = 0; i < ns; ++i) cflag[(size_t)i * kScal] = sel[i] ? 1.0 : 0.0;
+    CRS_HIP(hipMemcpyAsync(e.cand.p, cflag.data(), hsb, hipMemcpyHostToDevice, s));
+    mirror(sel);
+    exec_apply(e, OP_A, e.xw.p, e.q.p, s, e.cand.p);
+    hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
+    dot_to(e, e.t.p, e.t.p, 4, s);
     CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
     CRS_HIP(hipStreamSynchronize(s));
-    if (use_graph && prof)
-      prof_account(it == 1 ? e.prof_first : e.prof_iter,
-                   [&](const ProfRecord& r) { return r.tag >= 0 ? group_work(e, r.tag, r.family, true) : r.work; });
-    bool cand = false;
+    ++e.stats.host_syncs;
+    bool restart = false;
     for (int i = 0; i < ns; ++i) {
-      sel[i] = 0;
-      if (!active[i]) continue;
-      if (hs[i * kScal + S_BREAK] != 0.0) {
+      if (!sel[i]) continue;
+      if (std::sqrt(hs[i * kScal + S_TMP] / bb[i]) <= rtol) {
         active[i] = 0;
-        status[i] = 2;
-        it_used[i] = it;
-        continue;
-      }
-      const double rel = std::sqrt(hs[i * kScal + S_RR] / bb[i]);
-      if (history) history[(size_t)(it - 1) * ns + i] = rel;
-      it_used[i] = it;
-      if (!std::isfinite(rel)) {
-        active[i] = 0;
-        status[i] = 2;
-        continue;
-      }
-      if (rel <= rtol) {
-        sel[i] = 1;
-        cand = true;
+        status[i] = 0;
+        sel[i] = 0;
+      } else {
+        active[i] = 1;
+        restart = true;  // keep sel[i] = 1: restart from the true residual
       }
     }
-    if (cand) {
-      // true residual of the candidates only: t = b - A x (the operator
-      // skips the other systems; their q and t are not used)
-      std::vector<double> cflag((size_t)ns * kScal, 0.0);  // lives past the sync that ends this block
-      for (int i = 0; i < ns; ++i) cflag[(size_t)i * kScal] = sel[i] ? 1.0 : 0.0;
-      CRS_HIP(hipMemcpyAsync(e.cand.p, cflag.data(), hsb, hipMemcpyHostToDevice, s));
-      mirror(sel);
-      exec_apply(e, OP_A, e.xw.p, e.q.p, s, e.cand.p);
-      hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.t.p, b, e.q.p, e.dsys.p, (const int*)nullptr);
-      dot_to(e, e.t.p, e.t.p, 4, s);
+    for (int i = 0; i < ns; ++i) {
+      hs[i * kScal + S_ACTIVE] = active[i];
+      hs[i * kScal + S_RESTART] = sel[i];
+    }
+    CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
+    if (restart) {
+      std::copy(sel.begin(), sel.end(), e.hsel);
+      CRS_HIP(hipMemcpyAsync(e.dsel.p, e.hsel, ns * sizeof(int), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.r.p, e.t.p, (const double*)nullptr, e.dsys.p,
+                         e.dsel.p);
+      CRS_HIP(hipGetLastError());
+    }
+    CRS_HIP(hipStreamSynchronize(s));
+  };
+  int it = 0;
+  if (!use_graph) {
+    // one iteration at a time, the host deciding after each
+    while (any_active() && it < maxiter) {
+      ++it;
+      mirror(active);
+      if (it > 1) iter_precond(e, precond, s);
+      iter_apply(e, s);
       CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
       CRS_HIP(hipStreamSynchronize(s));
-      bool restart = false;
+      ++e.stats.host_syncs;
+      bool cand = false;
       for (int i = 0; i < ns; ++i) {
-        if (!sel[i]) continue;
-        if (std::sqrt(hs[i * kScal + S_TMP] / bb[i]) <= rtol) {
+        sel[i] = 0;
+        if (!active[i]) continue;
+        if (hs[i * kScal + S_BREAK] != 0.0) {
           active[i] = 0;
-          status[i] = 0;
-          sel[i] = 0;
-        } else {
-          restart = true;  // keep sel[i] = 1: restart from the true residual
+          status[i] = 2;
+          it_used[i] = it;
+          continue;
+        }
+        const double rel = std::sqrt(hs[i * kScal + S_RR] / bb[i]);
+        if (history) history[(size_t)(it - 1) * ns + i] = rel;
+        it_used[i] = it;
+        if (!std::isfinite(rel)) {
+          active[i] = 0;
+          status[i] = 2;
+          continue;
+        }
+        if (rel <= rtol) {
+          sel[i] = 1;
+          cand = true;
         }
       }
-      for (int i = 0; i < ns; ++i) {
-        hs[i * kScal + S_ACTIVE] = active[i];
-        hs[i * kScal + S_RESTART] = sel[i];
-      }
-      CRS_HIP(hipMemcpyAsync(e.scal.p, hs, hsb, hipMemcpyHostToDevice, s));
-      if (restart) {
-        std::copy(sel.begin(), sel.end(), e.hsel);
-        CRS_HIP(hipMemcpyAsync(e.dsel.p, e.hsel, ns * sizeof(int), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_sub_sel, vgrid(ns), dim3(256), 0, s, e.r.p, e.t.p, (const double*)nullptr, e.dsys.p,
-                           e.dsel.p);
-        CRS_HIP(hipGetLastError());
-      }
-      CRS_HIP(hipStreamSynchronize(s));
+      if (cand) true_residual_check();
     }
+  } else {
+    // chunks of up to kChunk iterations per graph launch: each iteration
+    // records its residuals and stops converged systems on the device; the
+    // host reads the flags between chunks, checks the candidates' true
+    // residuals and restarts the ones that fail.  Groups whose systems have
+    // all finished are left out of the captured chunk (a new graph is
+    // captured when that set changes; graphs are kept per key for reuse).
+    if (!e.cap_stream) CRS_HIP(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = e.cap_stream;
+    e.bbdev.upload(bb, s);
+    std::vector<double> hrow((size_t)kChunk * ns), hcand(ns);
+    auto get_graph = [&](bool first, int k) -> Exec::GraphEntry& {
+      uint64_t mask = 0;
+      for (int gi = 0; gi < ng && gi < 64; ++gi)
+        if (e.live[gi]) mask |= uint64_t(1) << gi;
+      const auto key = std::make_tuple(precond * 2 + (prof ? 1 : 0), first ? 1 : 0, k, mask);
+      auto itg = e.graphs.find(key);
+      if (itg != e.graphs.end() && itg->second->rtol == rtol) return *itg->second;
+      auto ge = std::make_unique<Exec::GraphEntry>();
+      ge->rtol = rtol;
+      const double rtol2 = rtol * rtol;
+      auto body = [&] {
+        for (int j = 0; j < k; ++j) {
+          double* row = e.hrows.p + (size_t)j * ns;
+          hipLaunchKernelGGL(k_chunk_start, dim3((ns + 255) / 256), dim3(256), 0, cs, e.scal.p, row, ns);
+          e.chunk_iter = j;
+          if (!(first && j == 0)) iter_precond(e, precond, cs);
+          iter_apply(e, cs);
+          hipLaunchKernelGGL(k_chunk_check, dim3((ns + 255) / 256), dim3(256), 0, cs, e.scal.p, e.bbdev.p,
+                             rtol2, row, e.dcand.p, ns);
+          CRS_HIP(hipGetLastError());
+        }
+        e.chunk_iter = 0;
+      };
+      try {
+        ge->exec = capture(e, cs, body, ge->prof);
+      } catch (const Error&) {
+        if (!prof) throw;
+        // the runtime refused event records inside the capture: capture
+        // without them (kernel timing is then unavailable inside graphs)
+        (void)hipGetLastError();
+        prof_disable_in_graphs();
+        ge->exec = capture(e, cs, body, ge->prof);
+      }
+      ++e.stats.graph_captures;
+      auto& ref = *ge;
+      e.graphs[key] = std::move(ge);
+      return ref;
+    };
+    while (any_active() && it < maxiter) {
+      const int k = std::min(kChunk, maxiter - it);
+      const bool first = it == 0;
+      // live groups: those with an active system
+      for (int gi = 0; gi < ng; ++gi) {
+        e.live[gi] = 0;
+        for (const SlotDev& sl : e.groups[gi].hslots)
+          if (active[sl.sys]) {
+            e.live[gi] = 1;
+            break;
+          }
+      }
+      Exec::GraphEntry& ge = get_graph(first, k);
+      std::fill(hcand.begin(), hcand.end(), 0.0);
+      CRS_HIP(hipMemcpyAsync(e.dcand.p, hcand.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
+      CRS_HIP(hipGraphLaunch(ge.exec, s));
+      ++e.stats.graph_launches;
+      CRS_HIP(hipMemcpyAsync(hs, e.scal.p, hsb, hipMemcpyDeviceToHost, s));
+      CRS_HIP(hipMemcpyAsync(hrow.data(), e.hrows.p, (size_t)k * ns * sizeof(double), hipMemcpyDeviceToHost, s));
+      CRS_HIP(hipMemcpyAsync(hcand.data(), e.dcand.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+      CRS_HIP(hipStreamSynchronize(s));
+      ++e.stats.host_syncs;
+      if (prof)
+        prof_account(ge.prof, [&](const ProfRecord& r) {
+          if (r.tag < 0) return r.work;
+          // tag = chunk iteration * 1024 + group: the systems that ran that iteration
+          const int j = r.tag / 1024, gi = r.tag % 1024;
+          for (int i = 0; i < ns; ++i) e.hact[i] = hrow[(size_t)j * ns + i] != -1.0 ? 1 : 0;
+          return group_work(e, gi, r.family, true);
+        });
+      bool cand = false;
+      for (int i = 0; i < ns; ++i) {
+        sel[i] = 0;
+        if (!active[i]) continue;
+        for (int j = 0; j < k; ++j) {
+          const double v = hrow[(size_t)j * ns + i];
+          if (v == -1.0) break;
+          it_used[i] = it + j + 1;
+          if (v >= 0.0 && history) history[(size_t)(it + j) * ns + i] = std::sqrt(v / bb[i]);
+        }
+        if (hs[i * kScal + S_BREAK] != 0.0) {
+          active[i] = 0;
+          status[i] = 2;
+          continue;
+        }
+        if (hcand[i] != 0.0) {
+          active[i] = 0;
+          sel[i] = 1;
+          cand = true;
+        }
+      }
+      it += k;
+      if (cand) true_residual_check();
+    }
+    it = 0;
+    for (int i = 0; i < ns; ++i) it = std::max(it, it_used[i]);
   }
+  e.stats.iterations = it;
   for (int i = 0; i < ns; ++i)
     if (active[i]) status[i] = 1;  // maxiter
   // final true residuals

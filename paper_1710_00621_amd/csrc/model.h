@@ -5,6 +5,8 @@
 
 #include "internal.h"
 
+#include <tuple>
+
 namespace crs {
 
 LegArgs leg_args(crs_grid g, ShtPlan& p);
@@ -101,6 +103,14 @@ struct ExecGroup {
   DevBuf<const double*> dptr, wptr;   // per map: data / omega_1 maps (right-hand side)
 };
 
+constexpr int kChunk = 8;         // PCG iterations per graph launch
+struct ExecStats {
+  int iterations = 0;             // iterations of the slowest system
+  int graph_launches = 0;
+  int graph_captures = 0;
+  int host_syncs = 0;             // host reads of the PCG flags
+};
+
 struct Exec {
   std::vector<crs_model> probs;   // not owned
   std::vector<SysDev> hsys;
@@ -131,11 +141,22 @@ struct Exec {
   double* hscal = nullptr;        // pinned host copy of the scalars [nsys][8]
   int* hsel = nullptr;            // pinned host selection flags [nsys]
   DevBuf<double> xw;              // iterate (the graphs reference only Exec buffers)
-  // captured iteration graphs (keyed by preconditioner and profiling)
+  // chunked graphs of the PCG iteration: k iterations per launch with the
+  // convergence test on the device (k_chunk_check); per chunk iteration a
+  // row of residuals (hrows), per system a candidate flag (dcand)
+  DevBuf<double> dcand, bbdev, hrows;
+  std::vector<char> live;         // per group: some system still iterating
+  int chunk_iter = 0;             // iteration within the chunk being captured
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<ProfRecord> prof;  // event pairs captured in the graph
+    double rtol = 0.0;
+    ~GraphEntry();
+  };
+  // keyed by (preconditioner and profiling, first chunk, iterations, live groups)
+  std::map<std::tuple<int, int, int, uint64_t>, std::unique_ptr<GraphEntry>> graphs;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_first = nullptr, graph_iter = nullptr;
-  int graph_key = -1;
-  std::vector<ProfRecord> prof_first, prof_iter;  // event pairs captured in the graphs
+  ExecStats stats;                // of the last exec_pcg
   ~Exec();
 };
 

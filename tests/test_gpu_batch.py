@@ -146,6 +146,11 @@ def test_batch_diag_matches_oracle(forced):
     batch = _with_env(env, lambda: crsolve.Batch(models))
     xg, infog = batch.solve(d=data, seeds=seeds, mode="cr", precond="diag", rtol=1e-12,
                             maxiter=5000, use_graph=True)
+    st = batch.stats()
+    # chunks of 8 iterations per graph launch, the host reading flags between them
+    assert st["iterations"] == max(infog["iters"])
+    assert st["graph_launches"] <= (st["iterations"] + 7) // 8 + 8, st
+    print(f"graph stats {st}", flush=True)
     xp, infop = batch.solve(d=data, seeds=seeds, mode="cr", precond="diag", rtol=1e-12,
                             maxiter=5000, use_graph=False)
     assert infog["status"] == 0 and infop["status"] == 0
