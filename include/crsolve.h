@@ -60,7 +60,7 @@ enum {
   CRS_EUNSUPPORTED = -6   /* valid request outside what the library supports */
 };
 
-enum { CRS_PRECOND_NONE = 0, CRS_PRECOND_DIAG = 1, CRS_PRECOND_PINV = 2 };
+enum { CRS_PRECOND_NONE = 0, CRS_PRECOND_DIAG = 1, CRS_PRECOND_PINV = 2, CRS_PRECOND_ADD = 3 };
 enum { CRS_MODE_WF = 0, CRS_MODE_CR = 1 };
 
 const char* crs_strerror(int status);
@@ -183,6 +183,38 @@ int crs_model_alpha2(crs_model m, double* alpha2);
 /* Replace the mixing matrix q (host, nbands x ncomp, row = band) and
  * recompute U^+ (and M_diag if present). */
 int crs_model_set_mixing(crs_model m, const double* q, crs_stream s);
+
+/* ------------------------------------------------ mask-restricted preconditioner
+ * M_mask = Z^T (Z S^-1 Z^T)^-1 Z (Sect. 4.2, eq:M_mask), Z = synthesis to the
+ * masked pixels of a HEALPix grid after the low-pass r_l = exp(-beta l^2
+ * (l+1)^2) with r_{L/2}^2 = lowpass_r2 (Sect. 4.3, eq:rl), L the components'
+ * band-limit; (Z S^-1 Z^T)^-1 approximated by the multigrid V-cycle of
+ * Sect. 4.4 (fig:code:mg, J taken as I): HEALPix levels with Nside and L
+ * halved, a coarse pixel masked when its four children are, Gaussian
+ * restriction of one coarse pixel FWHM, smoother omega / diag(G), bottom at
+ * the first level with fewer than nbottom masked pixels solved by the
+ * pseudo-inverse of its dense G (eigenvalues below rcond * max dropped).
+ * Each component with a prior gets its own cycle; those components must
+ * share one band-limit (else CRS_EUNSUPPORTED).  The preconditioner
+ * CRS_PRECOND_ADD is M_add = M_PI + M_mask (Sect. 4.2).
+ * crs_model_set_mask: grid: HEALPix; mask: host, npix bytes, nonzero =
+ * masked; opts: NULL or fields 0 for the defaults (0.05, 0.2, 1000, 1e-6).
+ * The grid must outlive the model.  Setup: allocates, builds the level grids
+ * and tables, eigendecomposes the bottom level on the device (rocSOLVER),
+ * synchronises the stream.
+ * crs_model_mask_info: number of levels and, per level, (Nside, L, masked
+ * pixels) into out (host, n ints; as many levels as fit).
+ * apply_mask_precond: z = M_mask r (device, nrhs x n). */
+typedef struct {
+  double lowpass_r2;
+  double omega;
+  int nbottom;
+  double rcond;
+} crs_mask_opts;
+int crs_model_set_mask(crs_model m, crs_grid grid, const uint8_t* mask, const crs_mask_opts* opts,
+                       crs_stream s);
+int crs_model_mask_info(crs_model m, int* nlevels, int* out, int n);
+int apply_mask_precond(crs_model m, int nrhs, const double* r, double* z, crs_stream s);
 
 /* Operators on nrhs stacked component vectors (device, nrhs x n, contiguous).
  * apply_A: y = A x (eq:A).  apply_pinv_precond: z = M_PI r.

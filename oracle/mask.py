@@ -119,10 +119,11 @@ class Level:
 
 def hierarchy(nside, mask, lmax, nbottom=1000):
     """Levels from the mask grid down to the first level with fewer than
-    nbottom masked pixels (or Nside 1 / band-limit 0)."""
+    nbottom masked pixels (or an odd Nside, or a band-limit below 2)."""
     mask = np.asarray(mask, dtype=bool)
     levels = [Level(nside, lmax, np.flatnonzero(mask))]
-    while len(levels[-1].idx) >= nbottom and levels[-1].nside >= 2 and levels[-1].lmax >= 2:
+    while (len(levels[-1].idx) >= nbottom and levels[-1].nside >= 2 and levels[-1].nside % 2 == 0
+           and levels[-1].lmax >= 2):
         h = levels[-1]
         ns_c = h.nside // 2
         par = parents(h.nside)

@@ -25,7 +25,7 @@ CRS_ENOTCONV = -4
 CRS_EBREAKDOWN = -5
 CRS_EUNSUPPORTED = -6
 
-PRECOND = {"none": 0, "diag": 1, "pinv": 2}
+PRECOND = {"none": 0, "diag": 1, "pinv": 2, "add": 3}
 MODE = {"wf": 0, "cr": 1}
 
 
@@ -38,6 +38,11 @@ class CrsError(RuntimeError):
 class BandDesc(ctypes.Structure):
     _fields_ = [("grid", vp), ("lmax", ctypes.c_int), ("beam", c_double_p),
                 ("tau", c_double_p), ("q", c_double_p)]
+
+
+class MaskOpts(ctypes.Structure):
+    _fields_ = [("lowpass_r2", ctypes.c_double), ("omega", ctypes.c_double),
+                ("nbottom", ctypes.c_int), ("rcond", ctypes.c_double)]
 
 
 class ModelDesc(ctypes.Structure):
@@ -69,6 +74,10 @@ _SIGS = {
     "crs_model_size": (ctypes.c_int, [vp, c_int64_p]),
     "crs_model_alpha2": (ctypes.c_int, [vp, c_double_p]),
     "crs_model_set_mixing": (ctypes.c_int, [vp, c_double_p, vp]),
+    "crs_model_set_mask": (ctypes.c_int, [vp, vp, ctypes.POINTER(ctypes.c_uint8),
+                                          ctypes.POINTER(MaskOpts), vp]),
+    "crs_model_mask_info": (ctypes.c_int, [vp, c_int_p, c_int_p, ctypes.c_int]),
+    "apply_mask_precond": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "apply_A": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "apply_pinv_precond": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "apply_diag_precond": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),

@@ -212,6 +212,28 @@ class Model:
         q, p = _host_f64(np.asarray(q, dtype=np.float64).reshape(self.nbands, self.ncomp))
         check(lib().crs_model_set_mixing(self._h, p, _stream()))
 
+    def set_mask(self, grid, mask, lowpass_r2=0.0, omega=0.0, nbottom=0, rcond=0.0):
+        """Build the mask-restricted preconditioner (M_mask; CRS_PRECOND_ADD =
+        M_PI + M_mask) on a HEALPix grid; mask: bool / uint8 per pixel (True =
+        masked).  Zero option values select the defaults."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if m.shape != (grid.npix,):
+            raise ValueError("mask must have one entry per pixel of the grid")
+        opts = _lib.MaskOpts(float(lowpass_r2), float(omega), int(nbottom), float(rcond))
+        check(lib().crs_model_set_mask(self._h, grid._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       ctypes.byref(opts), _stream()))
+        self.mask_grid = grid
+
+    def mask_info(self):
+        """[(Nside, L, masked pixels)] per level of the mask multigrid."""
+        nl = ctypes.c_int()
+        out = (ctypes.c_int * 96)()
+        check(lib().crs_model_mask_info(self._h, ctypes.byref(nl), out, 96))
+        return [tuple(out[3 * h:3 * h + 3]) for h in range(min(nl.value, 32))]
+
+    def apply_mask(self, r):
+        return self._op(lib().apply_mask_precond, r, "r")
+
     def _vec(self, x, name):
         x2, sq = _as2d(x)
         if x2.shape[1] != self.n:
@@ -460,6 +482,13 @@ def kernel_work_counts(family):
 
 def kernel_stats_reset():
     check(lib().crs_kernel_stats_reset())
+
+
+def mask_of_problem(problem, taus, grids):
+    """(grid, mask) for the mask preconditioner: the finest band's HEALPix grid
+    and its masked pixels (tau = 0)."""
+    nu = max(range(len(taus)), key=lambda i: len(taus[i]))
+    return grids[nu], np.asarray(taus[nu]) == 0.0
 
 
 def model_from_problem(problem, taus, grids=None, diag=True):

@@ -912,6 +912,10 @@ namespace {
 void precond_apply(Exec& e, int precond, const double* r, double* z, hipStream_t s, const double* act = nullptr) {
   if (precond == CRS_PRECOND_PINV) {
     exec_apply(e, OP_PI, r, z, s, act);
+  } else if (precond == CRS_PRECOND_ADD) {
+    // M_add = M_PI + M_mask (Sect. 4.2)
+    exec_apply(e, OP_PI, r, z, s, act);
+    exec_mask(e, r, z, true, s, act);
   } else if (precond == CRS_PRECOND_DIAG) {
     exec_diag(e, r, z, s, act);
   } else {
@@ -931,6 +935,9 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
   } else if (precond == CRS_PRECOND_DIAG) {
     exec_diag(e, e.r.p, e.z.p, s, act, e.wpart.p);
     hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 1, e.wpart.p, e.rng_sys.p, e.scal.p);
+  } else if (precond == CRS_PRECOND_ADD) {
+    precond_apply(e, precond, e.r.p, e.z.p, s, act);
+    dot_to(e, e.r.p, e.z.p, 1, s, act);
   } else {
     precond_apply(e, precond, e.r.p, e.z.p, s, act);
     dot_to(e, e.r.p, e.z.p, 1, s, act);
@@ -1023,9 +1030,12 @@ Exec::GraphEntry::~GraphEntry() {
 
 int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,
              double* relres, double* history, bool use_graph, hipStream_t s) {
-  CRS_CHECK(precond == CRS_PRECOND_NONE || precond == CRS_PRECOND_DIAG || precond == CRS_PRECOND_PINV,
+  CRS_CHECK(precond == CRS_PRECOND_NONE || precond == CRS_PRECOND_DIAG || precond == CRS_PRECOND_PINV ||
+                precond == CRS_PRECOND_ADD,
             CRS_EINVAL, "unknown preconditioner");
   CRS_CHECK(precond != CRS_PRECOND_DIAG || e.has_diag, CRS_EINVAL, "model was created without CRS_MODEL_DIAG");
+  CRS_CHECK(precond != CRS_PRECOND_ADD || exec_has_mask(e), CRS_EINVAL,
+            "M_add needs a mask preconditioner on every model (crs_model_set_mask)");
   CRS_CHECK(rtol > 0.0 && maxiter >= 0, CRS_EINVAL, "rtol must be > 0 and maxiter >= 0");
   const int ns = e.nsys;
   const int ng = (int)e.groups.size();

@@ -103,6 +103,17 @@ struct ExecGroup {
   DevBuf<const double*> dptr, wptr;   // per map: data / omega_1 maps (right-hand side)
 };
 
+// Mask-restricted preconditioner (mask.hip): the multigrid hierarchy of a
+// model and the per-Exec state of its cycle.
+struct MaskMG;
+struct MaskRun;
+struct MaskMGDel {
+  void operator()(MaskMG* p) const;
+};
+struct MaskRunDel {
+  void operator()(MaskRun* p) const;
+};
+
 constexpr int kChunk = 8;         // PCG iterations per graph launch
 struct ExecStats {
   int iterations = 0;             // iterations of the slowest system
@@ -157,6 +168,7 @@ struct Exec {
   std::map<std::tuple<int, int, int, uint64_t>, std::unique_ptr<GraphEntry>> graphs;
   hipStream_t cap_stream = nullptr;
   ExecStats stats;                // of the last exec_pcg
+  std::vector<std::unique_ptr<MaskRun, MaskRunDel>> mask_runs;  // per problem (M_mask)
   ~Exec();
 };
 
@@ -209,6 +221,13 @@ void exec_noise_weight(Exec& e, double scale, const std::vector<std::vector<cons
 int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int maxiter, int* iters,
              double* relres, double* history, bool use_graph, hipStream_t s);
 
+// z (+)= M_mask r on every system whose problem has a mask preconditioner
+// (act: skip finished systems, NULL: all)
+void exec_mask(Exec& e, const double* r, double* z, bool accumulate, hipStream_t s, const double* act);
+bool exec_has_mask(const Exec& e);
+// the model's Exec for nrhs right-hand sides (built on first use)
+Exec& model_exec_ref(crs_model m, int nrhs, hipStream_t s);
+
 void launch_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, int nrhs, int64_t n,
                            double* out, hipStream_t s);
 void model_draw_omegas(crs_model m, int nrhs, uint64_t seed, std::vector<const double*>& w1,
@@ -239,5 +258,6 @@ struct crs_model_s {
   // execution state for this model alone, per right-hand-side count, and CR draws
   std::map<int, std::unique_ptr<crs::Exec>> execs;
   crs::DevBuf<double> om1, om2, bcr;
+  std::unique_ptr<crs::MaskMG, crs::MaskMGDel> mask;  // M_mask hierarchy (crs_model_set_mask)
   int device = 0;
 };

@@ -308,6 +308,8 @@ std::vector<std::vector<const double*>> sys_band_ptrs(crs_model m, int nrhs, con
 }  // namespace
 
 namespace crs {
+Exec& model_exec_ref(crs_model m, int nrhs, hipStream_t s) { return model_exec(m, nrhs, s); }
+
 void launch_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, int nrhs, int64_t n, double* out,
                            hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
