@@ -62,6 +62,10 @@ def build_workload(name, nprob, crsolve, inputs, torch, dev):
         gl = [grid(b["grid"]) for b in prob["bands"]]
         taus = inputs.inverse_noise_maps(prob, lambda spec: grid(spec).pixel_centres())
         model = crsolve.model_from_problem(prob, taus, gl, diag=True)
+        if prob["mask"] is not None:
+            # the mask-restricted preconditioner of M_add (setup, outside the timed region)
+            mgrid, mk = crsolve.mask_of_problem(prob, taus, gl)
+            model.set_mask(mgrid, mk)
         s = torch.tensor(inputs.signal_coefficients(prob), device=dev)
         sig_maps = model.project(s)
         d = []
@@ -159,6 +163,19 @@ def _sht_work(prob):
     return sum(inputs.grid_nring(b["grid"]) * (b["lmax"] + 1) ** 2 for b in prob["bands"])
 
 
+def _oracle_precond(om, precond, prob, taus):
+    import numpy as np
+
+    from oracle import mask as omask, precond as opc
+    if precond == "diag":
+        return opc.DiagonalPrecond(om)
+    Mp = opc.PseudoInversePrecond(om)
+    if precond == "pinv":
+        return Mp
+    nu = max(range(len(taus)), key=lambda i: len(taus[i]))
+    return omask.AddPrecond(Mp, omask.MaskPrecond(om, prob["bands"][nu]["grid"][1], np.asarray(taus[nu]) == 0))
+
+
 def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
     """The oracle (numpy FP64, as it stands) timed on the host on a bounded
     sample, in ms per RHS.  For a single large problem the sample is one PCG
@@ -185,7 +202,7 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
 
         taus = inputs.inverse_noise_maps(prob, centres)
         om = _oracle_model(prob, taus)
-        M = opc.PseudoInversePrecond(om) if precond == "pinv" else opc.DiagonalPrecond(om)
+        M = _oracle_precond(om, precond, prob, taus)
         v = np.random.default_rng(0).standard_normal(om.n)
         t0 = time.perf_counter()
         om.apply_A(v)
@@ -216,7 +233,7 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
 
         taus = p["taus"] if scale == 1 else inputs.inverse_noise_maps(prob, centres)
         om = _oracle_model(prob, taus)
-        M = opc.PseudoInversePrecond(om) if precond == "pinv" else opc.DiagonalPrecond(om)
+        M = _oracle_precond(om, precond, prob, taus)
         v = np.random.default_rng(0).standard_normal(om.n)
         t0 = time.perf_counter()
         om.apply_A(v)
@@ -311,7 +328,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched", choices=["batched", "multires", "masked"])
     ap.add_argument("--nprob", type=int, default=64)
-    ap.add_argument("--precond", default=None, choices=["pinv", "diag"])
+    ap.add_argument("--precond", default=None, choices=["pinv", "diag", "add"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=5000)
     ap.add_argument("--pinv-maxiter", type=int, default=3000,
@@ -331,7 +348,7 @@ def main():
               "across GPUs (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if a.precond is None:
-        a.precond = "diag" if a.workload == "batched" else "pinv"
+        a.precond = {"batched": "diag", "masked": "add"}.get(a.workload, "pinv")
     if a.workload != "batched":
         a.nprob = 1
 
@@ -422,6 +439,18 @@ def main():
                 "note": "M_PI on the same masked batch (tau^+ = 0 in the mask); a time to solution "
                         "only when converged"}
             log(f"batched pinv: {extra['batched_pinv']}")
+        # the mask-restricted M_add on every problem, one solve each (plain)
+        if a.precond != "add":
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            it_a = solve_all(probs, "add", a.rtol, a.maxiter, torch)
+            torch.cuda.synchronize()
+            extra["plain_add"] = {
+                "ms_per_rhs": (time.perf_counter() - ta) * 1e3 / nrhs, "iterations_max": max(it_a),
+                "iterations_mean": sum(it_a) / nrhs, "iterations_sum": int(sum(it_a)),
+                "note": "M_add = M_PI + M_mask (multigrid V-cycle on the mask), one constrained_realization "
+                        "per problem without graphs; compare plain_ms_per_rhs / plain_iterations_sum (M_diag)"}
+            log(f"plain add: {extra['plain_add']}")
         # the pseudo-inverse preconditioner on the smallest problem (bounded)
         if a.precond != "pinv":
             small = min(probs, key=lambda p: p["model"].n)
@@ -461,6 +490,21 @@ def main():
             extra["ms_per_iteration"] = ms_per_step / max(1, sum(iters))
             log(f"not converged to {a.rtol} in {a.maxiter} iterations: relres {extra['final_relres']}")
         log(f"timed {a.steps} steps: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+        if a.workload == "masked":
+            # the other preconditioners for five times as many iterations (they
+            # do not reach rtol under the mask): residual reached and time per iteration
+            comp = {}
+            for pc in [p_ for p_ in ("diag", "pinv") if p_ != a.precond]:
+                cap = 5 * max(iters)
+                torch.cuda.synchronize()
+                tc = time.perf_counter()
+                itc = solve_all(probs, pc, a.rtol, cap, torch, allow_notconv=True)
+                torch.cuda.synchronize()
+                dtc = (time.perf_counter() - tc) * 1e3
+                comp[pc] = {"iterations": itc[0], "converged": probs[0]["status"] == 0,
+                            "relres": probs[0]["relres"], "ms_per_iteration": dtc / max(1, itc[0])}
+                log(f"masked with {pc}: {comp[pc]}")
+            extra["preconditioner_comparison"] = comp
 
     if a.workload != "multires" and not a.no_multires:
         mp, _ = build_workload("multires", 1, crsolve, inputs, torch, dev)

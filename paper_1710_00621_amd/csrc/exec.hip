@@ -1041,6 +1041,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
   const int ng = (int)e.groups.size();
   const size_t bytes = (size_t)e.ntot * sizeof(double);
   e.stats = ExecStats{};
+  if (precond == CRS_PRECOND_ADD) exec_mask_prepare(e, s);
   // scalars and flags go through pinned host memory (plain DMA transfers)
   double* const hs = e.hscal;
   const size_t hsb = (size_t)ns * kScal * sizeof(double);

@@ -633,6 +633,11 @@ void exec_mask(Exec& e, const double* r, double* z, bool accumulate, hipStream_t
   }
 }
 
+void exec_mask_prepare(Exec& e, hipStream_t s) {
+  for (int p = 0; p < (int)e.probs.size(); ++p)
+    if (e.probs[p]->mask) mask_run(e, p, s);
+}
+
 bool exec_has_mask(const Exec& e) {
   for (const crs_model m : e.probs)
     if (!m->mask) return false;

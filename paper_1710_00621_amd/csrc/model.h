@@ -225,6 +225,8 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
 // (act: skip finished systems, NULL: all)
 void exec_mask(Exec& e, const double* r, double* z, bool accumulate, hipStream_t s, const double* act);
 bool exec_has_mask(const Exec& e);
+// allocates the cycle state of every masked problem of e (before any capture)
+void exec_mask_prepare(Exec& e, hipStream_t s);
 // the model's Exec for nrhs right-hand sides (built on first use)
 Exec& model_exec_ref(crs_model m, int nrhs, hipStream_t s);
 

@@ -90,3 +90,38 @@ def test_pcg_add_matches_oracle(name, scale, index):
     print(f"  iterations gpu {info['iters'][0]} oracle {ref.iters}; max-abs rel {err:.2e}", flush=True)
     assert err < 1e-8
     assert abs(info["iters"][0] - ref.iters) <= 2
+
+
+def test_batch_add_matches_per_model_solves():
+    """M_add through a batch of small problems (graphs and no graphs) equals
+    each model's own M_add solve."""
+    torch, crsolve = _setup()
+    print("case batch M_add", flush=True)
+    grids, models, data, probs = {}, [], [], []
+    for i in range(4):
+        prob = inputs.make_problem("batched", scale=8, index=i)
+        om, taus = oracle_model(prob)
+        gl = []
+        for b in prob["bands"]:
+            if b["grid"] not in grids:
+                grids[b["grid"]] = crsolve.Grid.from_spec(b["grid"])
+            gl.append(grids[b["grid"]])
+        m = crsolve.model_from_problem(prob, taus, gl, diag=False)
+        mg, mk = crsolve.mask_of_problem(prob, taus, gl)
+        m.set_mask(mg, mk)
+        _, d = synthetic_data(prob, om)
+        models.append(m)
+        probs.append(prob)
+        data.append([torch.tensor(v, device="cuda") for v in d])
+    seeds = [77 + i for i in range(4)]
+    batch = crsolve.Batch(models)
+    xg, ig = batch.solve(d=data, seeds=seeds, mode="cr", precond="add", rtol=1e-11, maxiter=3000, use_graph=True)
+    xp, ip = batch.solve(d=data, seeds=seeds, mode="cr", precond="add", rtol=1e-11, maxiter=3000, use_graph=False)
+    assert ig["status"] == 0 and ip["status"] == 0
+    for p, m in enumerate(models):
+        xr, ir = m.constrained_realization([t.unsqueeze(0) for t in data[p]], seeds[p], mode="cr",
+                                           precond="add", rtol=1e-11, maxiter=3000)
+        a, b, c = xg[p].cpu().numpy(), xp[p].cpu().numpy(), xr[0].cpu().numpy()
+        print(f"problem {p}: iterations batch {ig['iters'][p]} model {ir['iters'][0]}", flush=True)
+        assert rel_max(a, c) < 1e-8 and rel_max(b, c) < 1e-8
+        assert abs(ig["iters"][p] - ir["iters"][0]) <= 1
