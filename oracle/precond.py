@@ -14,6 +14,16 @@ Pseudo-inverse preconditioner, Sect. 3.3:
         T^+ = blockdiag( alpha_nu^2 Y_nu^T W N_nu W Y_nu ,  I ).
     N_nu = diag(1/tau) is read as the pseudo-inverse of diag(tau): entries
     with tau = 0 (mask) are 0.
+Observation merging (App. A.3): bands whose rows of U are (nearly)
+proportional and whose normalised inverse-noise operators agree can share
+one row in the preconditioner.  Each merge group keeps its first band (the
+representative) with the row scaled by sqrt(1 + sum_nu gamma_{nu,l}^2),
+gamma_{nu,l} the least-squares scale of band nu's row onto the
+representative's at multipole l (the printed factor (gamma + 1)^{1/2} is read
+as (1 + gamma^2)^{1/2}, the value for which the merged normal equations equal
+the unmerged ones); the other bands of the group drop out of U^+ and T^+, so
+T^+ needs the representative's SHTs only.  When the rows are exactly
+proportional and the normalised noise operators equal, M_PI is unchanged.
 Block-diagonal preconditioner, Sect. 5:
     M_diag = (U^T diag(T) U)^-1, one N_comp x N_comp block per (l, m, part);
     the alpha factors cancel, leaving
@@ -55,12 +65,32 @@ def u_blocks(model, alpha2):
     return U
 
 
-def u_pinv(model, alpha2):
+def merge_rows(U, nb, merge):
+    """Merged band rows of U (App. A.3): per group, the representative's row
+    scaled by sqrt(1 + sum gamma_{nu,l}^2) and the other rows zeroed."""
+    U = U.copy()
+    for grp in merge or []:
+        rep = grp[0]
+        for l in range(U.shape[0]):
+            u0 = U[l, rep]
+            n0 = float(u0 @ u0)
+            if n0 == 0.0:
+                continue
+            g2 = 0.0
+            for nu in grp[1:]:
+                g = float(U[l, nu] @ u0) / n0
+                g2 += g * g
+                U[l, nu] = 0.0
+            U[l, rep] = math.sqrt(1.0 + g2) * u0
+    return U
+
+
+def u_pinv(model, alpha2, merge=None):
     """U_l^+ for every l, as [Lmax+1, ncomp, nbands + ncomp].
 
     Inactive columns (l > L_k) are dropped before the pseudo-inverse and
     come back as zero rows; all-zero rows of U_l give zero columns."""
-    U = u_blocks(model, alpha2)
+    U = merge_rows(u_blocks(model, alpha2), len(model.bands), merge)
     nc = len(model.comps)
     lmax = U.shape[0] - 1
     P = np.zeros((lmax + 1, nc, U.shape[1]))
@@ -73,14 +103,16 @@ def u_pinv(model, alpha2):
 
 
 class PseudoInversePrecond:
-    """M_PI of eq:fullmodel-preconditioner."""
+    """M_PI of eq:fullmodel-preconditioner (merge: optional list of band
+    groups merged as in App. A.3)."""
 
-    def __init__(self, model):
+    def __init__(self, model, merge=None):
         self.model = model
         nb = len(model.bands)
         self.alpha2 = np.array([alpha_squared(b["tau"], b["grid"].pixel_weights())
                                 for b in model.bands])
-        self.upinv = u_pinv(model, self.alpha2)
+        self.upinv = u_pinv(model, self.alpha2, merge)
+        self.dropped = set(nu for grp in (merge or []) for nu in grp[1:])
         # T^+ pixel weight: alpha^2 W N W = alpha^2 w^2 tau^+
         self.tplus_w = []
         for nu, b in enumerate(model.bands):
@@ -137,7 +169,8 @@ class PseudoInversePrecond:
 
     def __call__(self, r):
         tb, tp = self.apply_ut(r)
-        tb = [self.apply_tplus_band(t, nu) for nu, t in enumerate(tb)]
+        tb = [np.zeros_like(t) if nu in self.dropped else self.apply_tplus_band(t, nu)
+              for nu, t in enumerate(tb)]
         return self.apply_u(tb, tp)
 
 

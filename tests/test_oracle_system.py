@@ -250,3 +250,57 @@ def test_box_muller_closed_forms():
     w = philox.raw_words(5, 0x101, 3, 8)
     ref = philox.box_muller(philox.uniforms(w).reshape(2, 4)).reshape(-1)
     np.testing.assert_array_equal(philox.normals(5, 0x101, 3, 8), ref)
+
+
+def _twin_band_model(scale_tau=2.5, beam_other=None, seed=9):
+    """Two components; band 1 is band 0 observed again (same grid, beam, SED)
+    with its inverse noise scaled: rows of U proportional, normalised noise
+    equal (the case of App. A.3)."""
+    rng = np.random.default_rng(seed)
+    g8, g4 = geometry.healpix(8), geometry.healpix(4)
+    tau = np.exp(0.5 * rng.standard_normal(g8.npix))
+    L = 12
+    beam = inputs.gaussian_beam(400.0, L)
+    bands = [{"grid": g8, "lmax": L, "beam": beam, "tau": tau},
+             {"grid": g8, "lmax": L, "beam": beam if beam_other is None else beam_other,
+              "tau": scale_tau * tau},
+             {"grid": g4, "lmax": 8, "beam": inputs.gaussian_beam(600.0, 8),
+              "tau": np.exp(0.5 * rng.standard_normal(g4.npix))}]
+    comps = [{"lmax": 12, "invcl": inputs.inv_cl("cmb", 12, amplitude=0.05)},
+             {"lmax": 12, "invcl": inputs.inv_cl("powerlaw", 12, amplitude=0.05)}]
+    q = np.array([[1.0, 0.7], [1.0, 0.7], [1.0, 1.9]])
+    return Model(bands, comps, q)
+
+
+def test_merged_observations_leave_pinv_unchanged_for_twin_bands():
+    """App. A.3: with U_2 = gamma U_1 and equal normalised noise the merged
+    preconditioner (one row sqrt(1 + gamma^2) U_1, band 2's SHTs dropped) is
+    the same operator as the unmerged one."""
+    mdl = _twin_band_model()
+    M0 = precond.PseudoInversePrecond(mdl)
+    M1 = precond.PseudoInversePrecond(mdl, merge=[[0, 1]])
+    assert M1.dropped == {1}
+    r = np.random.default_rng(2).standard_normal((3, mdl.n))
+    for v in r:
+        np.testing.assert_allclose(M1(v), M0(v), rtol=1e-11, atol=1e-12 * np.abs(M0(v)).max())
+    # gamma is the ratio of the rows: sqrt(alpha_2^2 / alpha_1^2) = sqrt(2.5)
+    U = precond.u_blocks(mdl, M0.alpha2)
+    Um = precond.merge_rows(U, 3, [[0, 1]])
+    np.testing.assert_allclose(Um[5, 0], math.sqrt(1.0 + 2.5) * U[5, 0], rtol=1e-13)
+    assert not np.any(Um[:, 1])
+
+
+def test_merged_observations_are_a_preconditioner_for_near_twins():
+    """Rows only nearly proportional (a slightly different beam): the merged
+    operator is a compromise that stays symmetric positive definite and still
+    solves the system."""
+    L = 12
+    mdl = _twin_band_model(beam_other=inputs.gaussian_beam(440.0, L))
+    M1 = precond.PseudoInversePrecond(mdl, merge=[[0, 1]])
+    n = mdl.n
+    M = np.stack([M1(e) for e in np.eye(n)], axis=1)
+    np.testing.assert_allclose(M, M.T, atol=1e-10 * np.abs(M).max())
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    b = mdl.apply_A(np.random.default_rng(5).standard_normal(n))
+    res = pcg.pcg(mdl.apply_A, M1, b, rtol=1e-10, maxiter=500)
+    assert res.status == "ok"
