@@ -184,6 +184,19 @@ int crs_model_alpha2(crs_model m, double* alpha2);
  * recompute U^+ (and M_diag if present). */
 int crs_model_set_mixing(crs_model m, const double* q, crs_stream s);
 
+/* Observation merging in the pseudo-inverse preconditioner (App. A.3):
+ * group: host array of nbands, the merge group of each band (-1 = not
+ * merged; NULL clears all merging).  Bands of one group must share grid and
+ * band-limit.  In each group the lowest band index keeps a row of U, scaled
+ * by sqrt(1 + sum gamma_l^2) with gamma_l the least-squares scale of each
+ * other member's row onto it at multipole l (the printed (gamma + 1)^{1/2}
+ * read as (1 + gamma^2)^{1/2}); the other members drop out of U^+ and T^+,
+ * so M_PI runs their SHTs no longer.  A and M_diag are unchanged.  Exact
+ * for bands whose rows are proportional and whose normalised inverse noise
+ * agrees (detector sub-sets of one channel); a compromise otherwise.
+ * Synchronises the stream; the model's operator state is rebuilt. */
+int crs_model_merge_observations(crs_model m, const int* group, crs_stream s);
+
 /* ------------------------------------------------ mask-restricted preconditioner
  * M_mask = Z^T (Z S^-1 Z^T)^-1 Z (Sect. 4.2, eq:M_mask), Z = synthesis to the
  * masked pixels of a HEALPix grid after the low-pass r_l = exp(-beta l^2

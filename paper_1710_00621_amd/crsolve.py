@@ -212,6 +212,19 @@ class Model:
         q, p = _host_f64(np.asarray(q, dtype=np.float64).reshape(self.nbands, self.ncomp))
         check(lib().crs_model_set_mixing(self._h, p, _stream()))
 
+    def merge_observations(self, groups):
+        """Merge bands in the pseudo-inverse preconditioner (App. A.3):
+        groups is a list of lists of band indices (None or [] clears)."""
+        if not groups:
+            check(lib().crs_model_merge_observations(self._h, None, _stream()))
+            return
+        g = [-1] * self.nbands
+        for gi, grp in enumerate(groups):
+            for nu in grp:
+                g[nu] = gi
+        arr = (ctypes.c_int * self.nbands)(*g)
+        check(lib().crs_model_merge_observations(self._h, arr, _stream()))
+
     def set_mask(self, grid, mask, lowpass_r2=0.0, omega=0.0, nbottom=0, rcond=0.0):
         """Build the mask-restricted preconditioner (M_mask; CRS_PRECOND_ADD =
         M_PI + M_mask) on a HEALPix grid; mask: bool / uint8 per pixel (True =

@@ -131,9 +131,9 @@ __global__ __launch_bounds__(256) void k_mix_back(double* __restrict__ y, const 
     const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
     const double fs = cm * P.ftab[tri_h(P.Lf, m) + ll];
     for (int nu = 0; nu < P.nb; ++nu) {
-      const int* bi = P.binfo + 5 * nu;
+      const int* bi = P.binfo + kBinfo * nu;
       const int L = bi[0];
-      if (l > L) continue;
+      if (l > L || (usep && bi[5])) continue;  // bands merged into another drop out of M_PI
       const int gmaps = bi[1], map = bi[2] + S.rhs * bi[4], nt = bi[3];
       const int64_t nalm = (int64_t)(L + 1) * (L + 1);
       const int64_t tstride = (int64_t)gmaps * nalm;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_dq(const double* __restrict__ va, int s
   const int nu = (blockIdx.x / nc) % nb;
   const int r = blockIdx.x / (nc * nb);
   const int Lk = P.lk[k];
-  const int* bi = P.binfo + 5 * nu;
+  const int* bi = P.binfo + kBinfo * nu;
   const int Lb = bi[0];
   const int Lm = min(Lk, Lb);
   const int64_t nalm = (int64_t)(Lb + 1) * (Lb + 1);
@@ -488,6 +488,15 @@ __global__ void k_scal_out(const double* __restrict__ scal, int nsys, double sca
   if (i < nsys) out[i] = scale * scal[i * kScal + S_TMP];
 }
 
+// per map of a group: flag[8 j] = keep[j] and (act == NULL or the map's system is active)
+__global__ void k_pi_flags(double* __restrict__ flag, const int* __restrict__ keep, const int* __restrict__ mapsys,
+                           const double* __restrict__ act, int nmaps) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nmaps) return;
+  const bool on = keep[j] != 0 && (act == nullptr || act[kScal * mapsys[j]] != 0.0);
+  flag[kActStride * j] = on ? 1.0 : 0.0;
+}
+
 inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
@@ -575,9 +584,21 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
       ta.push_back(b.tau.p);
     }
     g.slots.upload(g.hslots, s);
-    std::vector<int> ms;
-    for (const SlotDev& sl : g.hslots) ms.push_back(sl.sys);
+    std::vector<int> ms, ident, keep;
+    g.pi_maps = 0;
+    for (const SlotDev& sl : g.hslots) {
+      ms.push_back(sl.sys);
+      ident.push_back((int)ident.size());
+      const crs_model pm = models[e->hsys[sl.sys].prob];
+      const int k = pm->pi_drop.empty() ? 1 : !pm->pi_drop[sl.band];
+      keep.push_back(k);
+      g.pi_maps += k;
+    }
     g.mapsys.upload(ms, s);
+    g.ident.upload(ident, s);
+    g.pikeep.upload(keep, s);
+    g.hkeep = keep;
+    g.piflag.alloc((size_t)kActStride * g.nmaps);
     g.wA.upload(wa, s);
     g.wP.upload(wp, s);
     g.tau.upload(ta, s);
@@ -590,15 +611,16 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   for (int p = 0; p < np; ++p) {
     const crs_model m = models[p];
     std::vector<const double*> vp(m->nbands);
-    std::vector<int> bi(5 * m->nbands);
+    std::vector<int> bi(kBinfo * m->nbands);
     for (int nu = 0; nu < m->nbands; ++nu) {
       const ExecGroup& g = e->groups[bgrp[p][nu]];
       vp[nu] = g.vpart.p;
-      bi[5 * nu + 0] = g.lmax;
-      bi[5 * nu + 1] = g.nmaps;
-      bi[5 * nu + 2] = bmap[p][nu];
-      bi[5 * nu + 3] = g.ntiles;
-      bi[5 * nu + 4] = 1;
+      bi[kBinfo * nu + 0] = g.lmax;
+      bi[kBinfo * nu + 1] = g.nmaps;
+      bi[kBinfo * nu + 2] = bmap[p][nu];
+      bi[kBinfo * nu + 3] = g.ntiles;
+      bi[kBinfo * nu + 4] = 1;
+      bi[kBinfo * nu + 5] = m->pi_drop.empty() ? 0 : m->pi_drop[nu];
     }
     e->vptr[p].upload(vp, s);
     e->binfo[p].upload(bi, s);
@@ -673,11 +695,12 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
 }
 
 namespace {
-// maps of group g whose system is active (all of them when not masked)
-int active_maps(const Exec& e, const ExecGroup& g, bool masked) {
-  if (!masked) return g.nmaps;
+// maps of group g whose system is active (all of them when not masked), and
+// for M_PI (pi) whose band is not merged into another band's row
+int active_maps(const Exec& e, const ExecGroup& g, bool masked, bool pi = false) {
   int n = 0;
-  for (const SlotDev& sl : g.hslots) n += e.hact[sl.sys] ? 1 : 0;
+  for (int j = 0; j < g.nmaps; ++j)
+    n += ((!masked || e.hact[g.hslots[j].sys]) && (!pi || g.hkeep[j])) ? 1 : 0;
   return n;
 }
 
@@ -688,9 +711,9 @@ bool capturing(hipStream_t s) {
 }  // namespace
 
 // Algorithmic work of one operator launch of group gi over its active maps.
-Work3 group_work(const Exec& e, int gi, int family, bool masked) {
+Work3 group_work(const Exec& e, int gi, int family, bool masked, bool pi) {
   const ExecGroup& g = e.groups[gi];
-  const int na = active_maps(e, g, masked);
+  const int na = active_maps(e, g, masked, pi);
   if (family == FAM_RING)
     return bytes_work(na * (ring_bytes(g.grid, g.lmax, 1, RING_ROUNDTRIP) + (double)g.grid->npix * 8.0));
   return leg_work(*g.plan, na);
@@ -708,9 +731,18 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
     // captured for
     if (skip_done && !cap && active_maps(e, g, true) == 0) continue;
     if (skip_done && cap && !e.live[gi]) continue;
-    const int tag = e.chunk_iter * 1024 + gi;
+    // M_PI of merged observations: the bands merged into another band skip T^+
+    const bool pimask = pinv && g.pi_maps < g.nmaps;
+    if (pinv && g.pi_maps == 0) continue;
+    const int tag = ((e.chunk_iter << 1) | (pinv ? 1 : 0)) * 1024 + gi;
     MapSkip skip;
-    if (skip_done) {
+    if (pimask) {
+      hipLaunchKernelGGL(k_pi_flags, dim3((g.nmaps + 255) / 256), dim3(256), 0, s, g.piflag.p, g.pikeep.p,
+                         g.mapsys.p, act, g.nmaps);
+      CRS_HIP(hipGetLastError());
+      skip.mapsys = g.ident.p;
+      skip.act = g.piflag.p;
+    } else if (skip_done) {
       skip.mapsys = g.mapsys.p;
       skip.act = act;
     }
@@ -721,16 +753,16 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
     {
-      ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done), s, tag);
+      ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done, pinv), s, tag);
       launch_leg_synth(g.leg, la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);
     }
     {
-      ProfScope ps(FAM_RING, group_work(e, gi, FAM_RING, skip_done), s, tag);
+      ProfScope ps(FAM_RING, group_work(e, gi, FAM_RING, skip_done, pinv), s, tag);
       launch_ring(g.grid, g.lmax, RING_ROUNDTRIP, g.nmaps, g.phase.p, g.pst, nullptr, nullptr, 0,
                   pinv ? g.wP.p : g.wA.p, 1, s, skip);
     }
     {
-      ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done), s, tag);
+      ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done, pinv), s, tag);
       launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
                          s);
     }
@@ -1235,10 +1267,10 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       if (prof)
         prof_account(ge.prof, [&](const ProfRecord& r) {
           if (r.tag < 0) return r.work;
-          // tag = chunk iteration * 1024 + group: the systems that ran that iteration
-          const int j = r.tag / 1024, gi = r.tag % 1024;
+          // tag = (chunk iteration, M_PI flag, group): the systems that ran that iteration
+          const int j = r.tag / 2048, pi = (r.tag / 1024) & 1, gi = r.tag % 1024;
           for (int i = 0; i < ns; ++i) e.hact[i] = hrow[(size_t)j * ns + i] != -1.0 ? 1 : 0;
-          return group_work(e, gi, r.family, true);
+          return group_work(e, gi, r.family, true, pi != 0);
         });
       bool cand = false;
       for (int i = 0; i < ns; ++i) {

@@ -47,6 +47,8 @@ __host__ __device__ inline void unpack_lm(int L, int64_t i, int& m, int& part, i
 // Work lists of the packed-index kernels: one entry per block, (row, first,
 // end) of a contiguous range of one row's packed indices.
 constexpr int kWorkBlock = 256;
+// per band of a problem in an Exec: {L, group maps, map base, tiles, map stride, dropped from M_PI}
+constexpr int kBinfo = 6;
 
 struct Band {
   crs_grid grid = nullptr;
@@ -97,6 +99,10 @@ struct ExecGroup {
   std::vector<SlotDev> hslots;
   DevBuf<SlotDev> slots;
   DevBuf<int> mapsys;                 // per map: its system
+  DevBuf<int> ident, pikeep;          // per map: its index; 1 if its band takes part in M_PI
+  DevBuf<double> piflag;              // per map (stride kActStride): runs in this M_PI launch
+  int pi_maps = 0;                    // maps whose band takes part in M_PI
+  std::vector<int> hkeep;             // host copy of pikeep
   DevBuf<const double*> wA, wP, tau;  // per map: tau, alpha^2 w^2 tau^+, tau
   DevBuf<double> uhat, vpart, pix;
   DevBuf<double2> phase;
@@ -192,7 +198,7 @@ void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double*
                double* wpart = nullptr);
 // algorithmic work of one launch of group gi (family FAM_*) over the maps
 // whose system is active in e.hact (masked) or over all of them
-Work3 group_work(const Exec& e, int gi, int family, bool masked);
+Work3 group_work(const Exec& e, int gi, int family, bool masked, bool pi = false);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
@@ -261,5 +267,7 @@ struct crs_model_s {
   std::map<int, std::unique_ptr<crs::Exec>> execs;
   crs::DevBuf<double> om1, om2, bcr;
   std::unique_ptr<crs::MaskMG, crs::MaskMGDel> mask;  // M_mask hierarchy (crs_model_set_mask)
+  std::vector<int> merge_group;      // per band: observation-merge group (-1: alone), App. A.3
+  std::vector<char> pi_drop;         // per band: merged into another band's row of U (no T^+)
   int device = 0;
 };

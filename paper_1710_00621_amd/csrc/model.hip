@@ -155,6 +155,27 @@ void build_pinv_tables(crs_model m, hipStream_t s) {
           U[(size_t)nu * na + ja] = std::sqrt(m->bands[nu].alpha2) * m->bands[nu].beam[l] * m->bands[nu].q[k];
       U[(size_t)(nb + k) * na + ja] = std::sqrt(m->invcl[k][l]);
     }
+    // merged observations (App. A.3): per group the representative's row
+    // scaled by sqrt(1 + sum gamma^2), gamma the least-squares scale of each
+    // other member's row onto it; the members' rows are zeroed
+    if (!m->merge_group.empty())
+      for (int rep = 0; rep < nb; ++rep) {
+        const int grp = m->merge_group[rep];
+        if (grp < 0 || m->pi_drop[rep]) continue;
+        double n0 = 0.0;
+        for (int ja = 0; ja < na; ++ja) n0 += U[(size_t)rep * na + ja] * U[(size_t)rep * na + ja];
+        double g2 = 0.0;
+        for (int nu = rep + 1; nu < nb; ++nu) {
+          if (m->merge_group[nu] != grp) continue;
+          double dot = 0.0;
+          for (int ja = 0; ja < na; ++ja) dot += U[(size_t)nu * na + ja] * U[(size_t)rep * na + ja];
+          const double g = n0 > 0.0 ? dot / n0 : 0.0;
+          g2 += g * g;
+          for (int ja = 0; ja < na; ++ja) U[(size_t)nu * na + ja] = 0.0;
+        }
+        const double sc = std::sqrt(1.0 + g2);
+        for (int ja = 0; ja < na; ++ja) U[(size_t)rep * na + ja] *= sc;
+      }
     small_pinv(U, rows, na, P);  // P: na x rows
     for (int ja = 0; ja < na; ++ja)
       for (int i = 0; i < rows; ++i) m->upinv[((size_t)l * nc + act[ja]) * rows + i] = P[(size_t)ja * rows + i];
@@ -444,6 +465,34 @@ int crs_model_set_mixing(crs_model m, const double* q, crs_stream st) {
     build_mix_tables(m, s);
     build_pinv_tables(m, s);
     if (m->has_diag) build_diag(m, s);
+    CRS_HIP(hipStreamSynchronize(s));
+    return CRS_OK;
+  });
+}
+
+int crs_model_merge_observations(crs_model m, const int* group, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(m != nullptr, CRS_EINVAL, "model is NULL");
+    hipStream_t s = (hipStream_t)st;
+    std::vector<int> grp(m->nbands, -1);
+    if (group)
+      for (int nu = 0; nu < m->nbands; ++nu) grp[nu] = group[nu] < 0 ? -1 : group[nu];
+    std::vector<char> drop(m->nbands, 0);
+    for (int nu = 0; nu < m->nbands; ++nu) {
+      if (grp[nu] < 0) continue;
+      for (int r = 0; r < nu; ++r)
+        if (grp[r] == grp[nu]) {
+          CRS_CHECK(m->bands[r].grid == m->bands[nu].grid && m->bands[r].lmax == m->bands[nu].lmax, CRS_EINVAL,
+                    "merged observations must share their grid and band-limit");
+          drop[nu] = 1;  // the lowest band index of a group keeps the row
+          break;
+        }
+    }
+    CRS_HIP(hipStreamSynchronize(s));
+    m->merge_group = grp;
+    m->pi_drop = drop;
+    build_pinv_tables(m, s);
+    m->execs.clear();  // per-band merge flags are part of every Exec's tables
     CRS_HIP(hipStreamSynchronize(s));
     return CRS_OK;
   });

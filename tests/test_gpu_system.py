@@ -241,3 +241,67 @@ def test_full_size_masked_apply_sampled():
     err = _rel(y[keep], yref[keep])
     print(f"sampled outputs {int(keep.sum())}, max-abs rel error {err:.2e}", flush=True)
     assert err < OP_TOL
+
+
+def _twin_models(beam_other_fwhm=None):
+    """GPU and oracle copies of a model whose band 1 repeats band 0 (same grid,
+    beam and SED, inverse noise scaled by 2.5); beam_other_fwhm gives band 1 a
+    slightly different beam (a near twin)."""
+    torch, crsolve = _setup()
+    from oracle import geometry as ogeo
+    from oracle.model import Model as OModel
+    rng = np.random.default_rng(9)
+    L = 12
+    g8, g4 = crsolve.Grid.healpix(8), crsolve.Grid.healpix(4)
+    o8, o4 = ogeo.healpix(8), ogeo.healpix(4)
+    tau = np.exp(0.5 * rng.standard_normal(o8.npix))
+    tau4 = np.exp(0.5 * rng.standard_normal(o4.npix))
+    beam = inputs.gaussian_beam(400.0, L)
+    beam1 = beam if beam_other_fwhm is None else inputs.gaussian_beam(beam_other_fwhm, L)
+    beam4 = inputs.gaussian_beam(600.0, 8)
+    comps = [{"lmax": 12, "invcl": inputs.inv_cl("cmb", 12, amplitude=0.05)},
+             {"lmax": 12, "invcl": inputs.inv_cl("powerlaw", 12, amplitude=0.05)}]
+    q = np.array([[1.0, 0.7], [1.0, 0.7], [1.0, 1.9]])
+    spec = [(g8, o8, L, beam, tau), (g8, o8, L, beam1, 2.5 * tau), (g4, o4, 8, beam4, tau4)]
+    gm = crsolve.Model([{"grid": g, "lmax": l, "beam": b, "tau": t} for g, _, l, b, t in spec], comps, q,
+                       diag=True)
+    om = OModel([{"grid": o, "lmax": l, "beam": b, "tau": t} for _, o, l, b, t in spec], comps, q)
+    gm._keep_grids = (g8, g4)
+    return om, gm
+
+
+def test_merged_observations_match_oracle():
+    """App. A.3 on the GPU: for twin bands the merged M_PI equals the unmerged
+    one and runs fewer Legendre flops; for near twins it matches the oracle's
+    merged operator, and a PCG solve with it matches the oracle's solve."""
+    torch, crsolve = _setup()
+    om, gm = _twin_models()
+    x = np.random.default_rng(3).standard_normal((2, om.n))
+    xt = torch.tensor(x, device="cuda")
+    crsolve.kernel_stats_reset()
+    crsolve.set_profiling(True)
+    z0 = gm.apply_pinv(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    w0 = crsolve.kernel_stats("legendre_synth")["work"]
+    gm.merge_observations([[0, 1]])
+    crsolve.kernel_stats_reset()
+    z1 = gm.apply_pinv(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    w1 = crsolve.kernel_stats("legendre_synth")["work"]
+    crsolve.set_profiling(False)
+    for i in range(2):
+        assert _rel(z1[i], z0[i]) < 1e-11
+    print(f"Legendre synthesis work unmerged {w0:.3e}, merged {w1:.3e}", flush=True)
+    assert w1 < w0  # band 1's T^+ transforms are no longer run
+    om2, gm2 = _twin_models(beam_other_fwhm=440.0)
+    gm2.merge_observations([[0, 1]])
+    Mref = precond.PseudoInversePrecond(om2, merge=[[0, 1]])
+    z2 = gm2.apply_pinv(xt).cpu().numpy()
+    for i in range(2):
+        assert _rel(z2[i], Mref(x[i])) < OP_TOL
+    b = om2.apply_A(x[0])
+    ref = pcg.pcg(om2.apply_A, Mref, b, rtol=1e-12, maxiter=500)
+    xs, info = gm2.pcg(torch.tensor(b, device="cuda"), precond="pinv", rtol=1e-12, maxiter=500)
+    assert ref.status == "ok" and info["status"] == 0
+    assert _rel(xs.cpu().numpy(), ref.x) < SOL_TOL
+    assert abs(info["iters"][0] - ref.iters) <= 2
