@@ -42,7 +42,14 @@ def dense_p(model, nu):
         # column map component layout -> band layout
         eye = np.eye(sht.nalm(c["lmax"]))
         R = sht.repack(eye, c["lmax"], b["lmax"])  # rows: comp idx, cols: band idx
-        P[:, model.offsets[k]:model.offsets[k + 1]] = model.q[nu, k] * (YB @ R.T)
+        if (nu, k) in getattr(model, "mixing_maps", {}):
+            # eq:Q: Q~ = Y^T W Q Y as a dense matrix on the pair's grid
+            grid, qmap = model.mixing_maps[(nu, k)]
+            Yg = dense_y(grid, c["lmax"])
+            Qt = Yg.T @ ((grid.pixel_weights() * np.asarray(qmap))[:, None] * Yg)
+            P[:, model.offsets[k]:model.offsets[k + 1]] = YB @ R.T @ Qt
+        else:
+            P[:, model.offsets[k]:model.offsets[k + 1]] = model.q[nu, k] * (YB @ R.T)
     return P
 
 

@@ -23,10 +23,13 @@ from . import sht
 
 
 class Model:
-    def __init__(self, bands, comps, q):
+    def __init__(self, bands, comps, q, mixing_maps=None):
         self.bands = bands
         self.comps = comps
         self.q = np.asarray(q, dtype=np.float64).reshape(len(bands), len(comps))
+        # spatially varying mixing (eq:Q): {(nu, k): (grid, q map)}; the pair's
+        # block of P is Y_nu B_nu Q~ with Q~ = Y^T W Q Y on that grid at L_k
+        self.mixing_maps = dict(mixing_maps or {})
         self.sizes = [sht.nalm(c["lmax"]) for c in comps]
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
         self.n = int(self.offsets[-1])
@@ -42,18 +45,29 @@ class Model:
         return np.concatenate(parts)
 
     # -- pieces of P (eq:P with Q~ = q I) --------------------------------
+    def mix(self, nu, k, xk):
+        """Q~_{nu,k} x_k (eq:Q): q_{nu,k} x_k for spatially constant mixing, else
+        Y^T W (q map) Y x_k on the pair's grid, output at the component's L_k."""
+        if (nu, k) not in self.mixing_maps:
+            return self.q[nu, k] * xk
+        grid, qmap = self.mixing_maps[(nu, k)]
+        L = self.comps[k]["lmax"]
+        f = sht.synth(grid, L, xk)
+        return sht.adjoint(grid, L, grid.pixel_weights() * np.asarray(qmap) * f)
+
     def to_band(self, x, nu):
-        """u_nu = B_nu sum_k q_{nu,k} x_k, in band nu's packed layout."""
+        """u_nu = B_nu sum_k Q~_{nu,k} x_k, in band nu's packed layout."""
         L = self.bands[nu]["lmax"]
         u = np.zeros(sht.nalm(L))
         for k, xk in enumerate(self.split(x)):
-            u += self.q[nu, k] * sht.repack(xk, self.comps[k]["lmax"], L)
+            u += sht.repack(self.mix(nu, k, xk), self.comps[k]["lmax"], L)
         return self.bands[nu]["beam"][self._ell_band[nu]] * u
 
     def from_band(self, v, nu):
-        """Transpose of to_band: component vector from a band vector."""
+        """Transpose of to_band: component vector from a band vector (Q~ is
+        symmetric: W and Q are both diagonal)."""
         bv = self.bands[nu]["beam"][self._ell_band[nu]] * v
-        parts = [self.q[nu, k] * sht.repack(bv, self.bands[nu]["lmax"], c["lmax"])
+        parts = [self.mix(nu, k, sht.repack(bv, self.bands[nu]["lmax"], c["lmax"]))
                  for k, c in enumerate(self.comps)]
         return self.join(parts)
 

@@ -48,19 +48,36 @@ def alpha_squared(tau, w):
     return float((t * t).sum() / s1)
 
 
+def optimal_q(qmap):
+    """App. A.2, eq:optimal-q: the scalar closest to a mixing map,
+    sum_i q_i^2 / sum_i q_i over the map's pixels."""
+    q = np.asarray(qmap, dtype=np.float64)
+    return float((q * q).sum() / q.sum())
+
+
+def effective_q(model):
+    """Mixing scalars of the preconditioners: q_{nu,k}, or eq:optimal-q of the
+    pair's mixing map where the mixing is spatially varying."""
+    q = model.q.copy()
+    for (nu, k), (_, qmap) in getattr(model, "mixing_maps", {}).items():
+        q[nu, k] = optimal_q(qmap)
+    return q
+
+
 def u_blocks(model, alpha2):
     """U_l for l = 0..Lmax as an array [Lmax+1, nbands + ncomp, ncomp]."""
     nb, nc = len(model.bands), len(model.comps)
     lmax = max(max(b["lmax"] for b in model.bands), max(c["lmax"] for c in model.comps))
     U = np.zeros((lmax + 1, nb + nc, nc))
     alpha = np.sqrt(np.asarray(alpha2, dtype=np.float64))
+    q = effective_q(model)
     for l in range(lmax + 1):
         for k, c in enumerate(model.comps):
             if l > c["lmax"]:
                 continue
             for nu, b in enumerate(model.bands):
                 if l <= b["lmax"]:
-                    U[l, nu, k] = alpha[nu] * b["beam"][l] * model.q[nu, k]
+                    U[l, nu, k] = alpha[nu] * b["beam"][l] * q[nu, k]
             U[l, nb + k, k] = math.sqrt(c["invcl"][l])
     return U
 
@@ -216,7 +233,8 @@ class DiagonalPrecond:
             ell_b = sht.lm_arrays(b["lmax"])[0]
             dg = dg * b["beam"][ell_b] ** 2
             dg = sht.repack(dg, b["lmax"], self.lu)
-            qq = np.outer(model.q[nu], model.q[nu])
+            qe = effective_q(model)[nu]
+            qq = np.outer(qe, qe)
             D += dg[:, None, None] * qq[None, :, :]
         active = np.zeros((nu_, nc))
         for k, c in enumerate(model.comps):

@@ -304,3 +304,48 @@ def test_merged_observations_are_a_preconditioner_for_near_twins():
     b = mdl.apply_A(np.random.default_rng(5).standard_normal(n))
     res = pcg.pcg(mdl.apply_A, M1, b, rtol=1e-10, maxiter=500)
     assert res.status == "ok"
+
+
+def _varmix_model(const=None, seed=13):
+    """Two bands, two components; the synchrotron-like component's mixing in
+    band 1 is a smooth map on a Gauss-Legendre grid (const: a flat map)."""
+    rng = np.random.default_rng(seed)
+    g8, g4 = geometry.healpix(8), geometry.healpix(4)
+    L = 10
+    bands = [{"grid": g8, "lmax": L, "beam": inputs.gaussian_beam(400.0, L),
+              "tau": np.exp(0.4 * rng.standard_normal(g8.npix))},
+             {"grid": g4, "lmax": 8, "beam": inputs.gaussian_beam(600.0, 8),
+              "tau": np.exp(0.4 * rng.standard_normal(g4.npix))}]
+    comps = [{"lmax": L, "invcl": inputs.inv_cl("cmb", L, amplitude=0.05)},
+             {"lmax": L, "invcl": inputs.inv_cl("powerlaw", L, amplitude=0.05)}]
+    q = np.array([[1.0, 0.8], [1.0, 1.7]])
+    gq = geometry.gauss_legendre(L + 1, 2 * L + 1)
+    z, phi = gq.pixel_centres()
+    qmap = np.full(gq.npix, const) if const is not None else 1.7 * (1.0 + 0.3 * z + 0.2 * np.cos(phi) * (1 - z * z))
+    return Model(bands, comps, q, mixing_maps={(1, 1): (gq, qmap)})
+
+
+def test_flat_mixing_map_equals_scalar_mixing():
+    """eq:Q with a flat map q on a Gauss-Legendre grid (exact quadrature at the
+    band-limit, Y^T W Y = I) is the scalar mixing q I."""
+    mdl = _varmix_model(const=1.7)
+    ref = Model(mdl.bands, mdl.comps, mdl.q)
+    x = np.random.default_rng(1).standard_normal(mdl.n)
+    np.testing.assert_allclose(mdl.apply_A(x), ref.apply_A(x), rtol=1e-12, atol=1e-12 * np.abs(ref.apply_A(x)).max())
+
+
+def test_varying_mixing_map_apply_a_matches_dense():
+    """A with a spatially varying mixing map against the dense A built from the
+    dense Y, Q~ = Y^T W Q Y, and its symmetry; the preconditioners use the
+    scalar of eq:optimal-q."""
+    mdl = _varmix_model()
+    A = dense.dense_a(mdl)
+    np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+    x = np.random.default_rng(2).standard_normal(mdl.n)
+    np.testing.assert_allclose(mdl.apply_A(x), A @ x, rtol=1e-11, atol=1e-12 * np.abs(A @ x).max())
+    qmap = mdl.mixing_maps[(1, 1)][1]
+    assert abs(precond.effective_q(mdl)[1, 1] - (qmap ** 2).sum() / qmap.sum()) < 1e-14
+    b = A @ x
+    res = pcg.pcg(mdl.apply_A, precond.PseudoInversePrecond(mdl), b, rtol=1e-11, maxiter=400)
+    assert res.status == "ok"
+    np.testing.assert_allclose(res.x, x, atol=1e-8 * np.abs(x).max())
