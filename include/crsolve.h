@@ -184,6 +184,23 @@ int crs_model_alpha2(crs_model m, double* alpha2);
  * recompute U^+ (and M_diag if present). */
 int crs_model_set_mixing(crs_model m, const double* q, crs_stream s);
 
+/* Spatially varying mixing (Sect. 2.2, eq:P, eq:Q): the block (band, comp)
+ * of P becomes Y_nu B_nu Q~ with Q~ = Y^T W Q Y, Q = diag(qmap) on grid (any
+ * of the library's grids; Gauss-Legendre gives an exact quadrature at the
+ * band-limit), applied at the component's band-limit L_k (the product's
+ * modes above L_k are dropped).  qmap: host, npix of grid, finite, positive
+ * sum; NULL returns the pair to its scalar q.  The pair's scalar in M_PI and
+ * M_diag becomes sum q^2 / sum q (App. A.2, eq:optimal-q).  Each varying pair
+ * adds four SHTs at L_k on its grid to every application of A (two before the
+ * forward mix, two after the transpose), and to build_rhs / project.
+ * A model with mask-in-mixing (Sect. 4.1) is the special case qmap = q (1 -
+ * mask).  Supported on single models (batches of such models return
+ * CRS_EUNSUPPORTED, and so do the mixing gradients apply_dA_dmix /
+ * apply_db_dmix).  The grid must outlive the model.  Synchronises the
+ * stream; the model's operator state is rebuilt. */
+int crs_model_set_mixing_map(crs_model m, int band, int comp, crs_grid grid, const double* qmap,
+                             crs_stream s);
+
 /* Observation merging in the pseudo-inverse preconditioner (App. A.3):
  * group: host array of nbands, the merge group of each band (-1 = not
  * merged; NULL clears all merging).  Bands of one group must share grid and

@@ -212,6 +212,18 @@ class Model:
         q, p = _host_f64(np.asarray(q, dtype=np.float64).reshape(self.nbands, self.ncomp))
         check(lib().crs_model_set_mixing(self._h, p, _stream()))
 
+    def set_mixing_map(self, band, comp, grid=None, qmap=None):
+        """Spatially varying mixing for (band, comp): Q~ = Y^T W diag(qmap) Y on
+        grid (eq:Q); qmap None returns the pair to its scalar q."""
+        if qmap is None:
+            check(lib().crs_model_set_mixing_map(self._h, int(band), int(comp), None, None, _stream()))
+            return
+        q, p = _host_f64(qmap)
+        if len(q) != grid.npix:
+            raise ValueError("qmap must have one value per pixel of grid")
+        check(lib().crs_model_set_mixing_map(self._h, int(band), int(comp), grid._h, p, _stream()))
+        self._mixgrids = getattr(self, "_mixgrids", []) + [grid]
+
     def merge_observations(self, groups):
         """Merge bands in the pseudo-inverse preconditioner (App. A.3):
         groups is a list of lists of band indices (None or [] clears)."""

@@ -66,8 +66,12 @@ __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict
       const int L = P.lk[k];
       if (l > L) continue;
       const double c = coef[((int64_t)l * P.nb + sl.band) * P.nc + k];
-      const int64_t idx = P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
-      acc = fma(c, xs[idx], acc);
+      const int64_t loc = moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      // a spatially varying pair reads y = Q~ x_k instead of x_k (eq:Q)
+      const int v = (!usep && P.vidx) ? P.vidx[sl.band * P.nc + k] : -1;
+      const double xv = v >= 0 ? P.ybuf[P.yoff[v] + (int64_t)S.rhs * (int64_t)(L + 1) * (L + 1) + loc]
+                               : xs[P.coff[k] + loc];
+      acc = fma(c, xv, acc);
     }
     const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
     uhat[(int64_t)map * nalm + i] = cm * P.ftab[tri_h(P.Lf, m) + ll] * acc;
@@ -151,9 +155,10 @@ __global__ __launch_bounds__(256) void k_mix_back(double* __restrict__ y, const 
       }
       for (; t < nt; ++t) sv += v[t * tstride];
       const double* cn = coef + ((int64_t)l * P.nb + nu) * nc;
+      const int* vb = (!usep && P.vidx) ? P.vidx + nu * nc : nullptr;  // varying pairs: added afterwards
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (k < nc && ix[k] >= 0) acc[k] = fma(cn[k] * fs, sv, acc[k]);
+        if (k < nc && ix[k] >= 0 && !(vb && vb[k] >= 0)) acc[k] = fma(cn[k] * fs, sv, acc[k]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -209,6 +214,36 @@ __global__ __launch_bounds__(256) void k_diag_apply(const double* __restrict__ r
     const double t = block_sum256(dacc, red);
     if (threadIdx.x == 0) wpart[blockIdx.x] = t;
   }
+}
+
+// wpart[b] = this work-list block's part of a . b over its packed indices of
+// every component (the partition k_mix_back uses for its fused dot)
+__global__ __launch_bounds__(256) void k_wl_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                                const SysDev* __restrict__ sys, const ProbDev* __restrict__ probs,
+                                                const int4* __restrict__ wl, const double* __restrict__ act,
+                                                double* __restrict__ wpart) {
+  __shared__ double red[4];
+  const int4 w = wl[blockIdx.x];
+  if (act && act[kScal * w.x] == 0.0) {
+    if (threadIdx.x == 0) wpart[blockIdx.x] = 0.0;
+    return;
+  }
+  const SysDev S = sys[w.x];
+  const ProbDev P = probs[S.prob];
+  double acc = 0.0;
+  for (int u = w.y + threadIdx.x; u < w.z; u += blockDim.x) {
+    int m, part, ll;
+    unpack_lm(P.Lc, u, m, part, ll);
+    const int l = m + ll;
+    for (int k = 0; k < P.nc; ++k) {
+      const int L = P.lk[k];
+      if (l > L) continue;
+      const int64_t i = S.off + P.coff[k] + moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
+      acc = fma(a[i], b[i], acc);
+    }
+  }
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) wpart[blockIdx.x] = t;
 }
 
 // y[sys][coff_k + idx] = C^-1_{k,l} x[sys][coff_k + idx] (work list over rows)
@@ -540,6 +575,11 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   e->nsys = (int)e->hsys.size();
   e->ntot = off;
   e->hact.assign(e->nsys, 1);
+  {
+    std::vector<int> id(e->nsys);
+    for (int i = 0; i < e->nsys; ++i) id[i] = i;
+    e->sys_ident.upload(id, s);
+  }
   // groups: maps (problem, band) x rhs, map = base + rhs
   std::map<std::pair<crs_grid, int>, int> gid;
   std::vector<std::vector<int>> bmap(np);  // per problem per band: map base
@@ -640,6 +680,21 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
     d.Dinv = m->has_diag ? m->Dinv.p : nullptr;
     d.vptr = e->vptr[p].p;
     d.binfo = e->binfo[p].p;
+    d.vidx = nullptr;
+    d.ybuf = nullptr;
+    d.yoff = nullptr;
+  }
+  if (!models.empty()) {
+    bool any = false;
+    for (const crs_model m : models) any = any || !m->varmix.empty();
+    CRS_CHECK(!any || models.size() == 1, CRS_EUNSUPPORTED,
+              "spatially varying mixing maps are supported on single models, not in batches");
+    if (any) exec_varmix_prepare(*e, s);  // sets the varying-pair fields of pd[0]
+    if (any) {
+      pd[0].vidx = e->vm_vidx;
+      pd[0].ybuf = e->vm_ybuf;
+      pd[0].yoff = e->vm_yoff;
+    }
   }
   e->dprobs.upload(pd, s);
   e->dsys.upload(e->hsys, s);
@@ -771,11 +826,23 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
 
 void exec_apply(Exec& e, OpKind kind, const double* in, double* out, hipStream_t s, const double* act,
                 double* wpart) {
+  const bool vm = kind == OP_A && exec_has_varmix(e);
+  if (vm) exec_varmix_fwd(e, in, s, act);
   exec_bands(e, kind, in, s, act);
-  if (kind == OP_PI)
+  if (kind == OP_PI) {
     mix_back(e, out, in, 2, 0, 1, s, act, wpart);
-  else
+  } else if (!vm) {
     mix_back(e, out, in, 1, 0, 0, s, act, wpart);
+  } else {
+    // the varying pairs add to out after the back-mix: the fused dot follows them
+    mix_back(e, out, in, 1, 0, 0, s, act, nullptr);
+    exec_varmix_back(e, out, s, act);
+    if (wpart) {
+      hipLaunchKernelGGL(k_wl_dot, dim3(e.nwl_sys), dim3(256), 0, s, in, out, e.dsys.p, e.dprobs.p, e.wl_sys.p, act,
+                         wpart);
+      CRS_HIP(hipGetLastError());
+    }
+  }
 }
 
 void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double* act, double* wpart) {
@@ -819,6 +886,7 @@ void exec_rhs(Exec& e, const std::vector<std::vector<const double*>>& d,
               hipStream_t s) {
   exec_rhs_bands(e, d, w1, s);
   mix_back(e, b, w2, w2 ? 1 : 0, 1, 0, s);
+  exec_varmix_back(e, b, s, nullptr);
 }
 
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s) {
@@ -839,6 +907,7 @@ void exec_mix_grad(Exec& e, const double* va, int sa0, const double* vb, int sb0
 }
 
 void exec_project(Exec& e, const double* x, const std::vector<std::vector<double*>>& maps, hipStream_t s) {
+  exec_varmix_fwd(e, x, s, nullptr);
   for (auto& g : e.groups) {
     const int64_t npix = g.grid->npix;
     g.pix.alloc((size_t)g.nmaps * npix);

@@ -73,87 +73,6 @@ void pixel_centres(crs_grid g, std::vector<double>& z, std::vector<double>& phi)
     }
 }
 
-// ------------------------------------------------------------ kernels
-// Harmonic vectors: packed m-major (unpack_lm / moff_h of model.h).  Maps of
-// a batch of nm vectors; map j skipped when skip.off(j).
-__device__ __forceinline__ int64_t repack_idx(int L, int m, int part, int ll) {
-  return moff_h(L, m) + (int64_t)part * (L - m + 1) + ll;
-}
-
-// out_hat[j][i] = hs[i] f_j[l] (in1_j + in2_j)[l, m, part]  (inputs at their own
-// band-limits, zero above them; in2 optional; f optional)
-__global__ void k_hat_from(double* __restrict__ out, int LO, const double* __restrict__ hs,
-                           const double* __restrict__ in1, int L1, const int64_t* __restrict__ off1, int64_t st1,
-                           const double* __restrict__ in2, int L2, int64_t st2,
-                           const double* __restrict__ F, int fst, const int* __restrict__ mc, MapSkip skip) {
-  const int j = blockIdx.y;
-  if (skip.off(j)) return;
-  const int64_t n = nalm_of(LO);
-  const double* a = in1 + (off1 ? off1[j] : (int64_t)j * st1);
-  const double* b = in2 ? in2 + (int64_t)j * st2 : nullptr;
-  const double* f = F ? F + (int64_t)mc[j] * fst : nullptr;
-  double* o = out + (int64_t)j * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int m, part, ll;
-    unpack_lm(LO, i, m, part, ll);
-    const int l = m + ll;
-    double v = (l <= L1) ? a[repack_idx(L1, m, part, l - m)] : 0.0;
-    if (b && l <= L2) v += b[repack_idx(L2, m, part, l - m)];
-    if (f) v *= f[l];
-    o[i] = hs[i] * v;
-  }
-}
-
-// out_j[i] = (acc ? out_j[i] : 0) + alpha f_j[l] hs[i] sum_t parts[t][j][i] - g_j[l] sub_j[l, m, part]
-// (adjoint partial sums at band-limit LO to a plain vector; f, sub optional)
-__global__ void k_from_parts(double* __restrict__ out, const int64_t* __restrict__ offo, int LO, int acc,
-                             double alpha, const double* __restrict__ hs, const double* __restrict__ parts, int ntiles,
-                             int64_t tstride, const double* __restrict__ F, int fst,
-                             const double* __restrict__ sub, int Ls, int64_t sst, const double* __restrict__ Gs,
-                             int gst, const int* __restrict__ mc, MapSkip skip) {
-  const int j = blockIdx.y;
-  if (skip.off(j)) return;
-  const int64_t n = nalm_of(LO);
-  double* o = out + (offo ? offo[j] : (int64_t)j * n);
-  const double* pp = parts + (int64_t)j * n;
-  const double* f = F ? F + (int64_t)mc[j] * fst : nullptr;
-  const double* sb = sub ? sub + (int64_t)j * sst : nullptr;
-  const double* g = Gs ? Gs + (int64_t)mc[j] * gst : nullptr;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double sv = 0.0;
-    for (int t = 0; t < ntiles; ++t) sv += pp[(int64_t)t * tstride + i];
-    int m, part, ll;
-    unpack_lm(LO, i, m, part, ll);
-    const int l = m + ll;
-    double v = alpha * hs[i] * sv;
-    if (f) v *= f[l];
-    if (sb) v -= (l <= Ls ? g[l] * sb[repack_idx(Ls, m, part, ll)] : 0.0);
-    o[i] = acc ? o[i] + v : v;
-  }
-}
-
-// pointwise map operations on nm maps of npix pixels (ind: 0/1 mask of the level)
-enum { MOP_MASK = 0, MOP_SCALE = 1, MOP_AXPY_MASK = 2, MOP_POST = 3, MOP_ZERO = 4 };
-__global__ void k_map_op(int op, double* __restrict__ x, const double* __restrict__ b, const double* __restrict__ y,
-                         const double* __restrict__ ind, const double* __restrict__ sm, double alpha, int64_t npix,
-                         MapSkip skip) {
-  const int j = blockIdx.y;
-  if (skip.off(j)) return;
-  double* xj = x + (int64_t)j * npix;
-  const double* bj = b ? b + (int64_t)j * npix : nullptr;
-  const double* yj = y ? y + (int64_t)j * npix : nullptr;
-  const double s = sm ? sm[j] : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
-    switch (op) {
-      case MOP_MASK: xj[i] *= ind[i]; break;
-      case MOP_SCALE: xj[i] = s * bj[i]; break;
-      case MOP_AXPY_MASK: xj[i] = fma(alpha * ind[i], yj[i], xj[i]); break;
-      case MOP_POST: xj[i] = fma(s, bj[i] - ind[i] * yj[i], xj[i]); break;
-      default: xj[i] = 0.0; break;
-    }
-  }
-}
-
 // bottom level: x_j[idx[i]] = sum_k Gp_c[i][k] b_j[idx[k]] (x_j is zero elsewhere)
 __global__ __launch_bounds__(256) void k_bottom(double* __restrict__ x, const double* __restrict__ b, int64_t npix,
                                                 const int* __restrict__ idx, int n,
@@ -187,12 +106,6 @@ __global__ void k_form_pinv(double* __restrict__ Gp, const double* __restrict__ 
   }
   Gp[(int64_t)i * n + jj] = acc;
 }
-
-dim3 alm_grid(int L, int nm) {
-  const int64_t n = nalm_of(L);
-  return dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048), nm);
-}
-dim3 map_grid(int64_t npix, int nm) { return dim3((unsigned)std::min<int64_t>((npix + 255) / 256, 2048), nm); }
 
 }  // namespace
 
@@ -237,11 +150,7 @@ struct MaskRunImpl {
   DevBuf<int64_t> off_top;                   // per map: offset of its component vector in the stacked vectors
   std::vector<DevBuf<double>> b, x, y, u, rt, ct;  // per level
   std::vector<DevBuf<double>> sm;            // per level: per-map smoother constant
-  DevBuf<double> hat, parts;
-  DevBuf<double2> phase;
-  // Legendre kernels per (grid, L), fixed when the buffers were sized (a later
-  // autotuning of the same shape must not change the tile count)
-  std::map<std::pair<crs_grid, int>, LegChoice> choice;
+  ShtScratch sc;                              // transform scratch of every level
 };
 
 }  // namespace
@@ -253,44 +162,16 @@ void MaskRunDel::operator()(MaskRun* p) const { delete p; }
 namespace {
 
 void synth_ws(crs_grid g, int L, int nm, const double* hat, double* map, MaskRun& r, MapSkip skip, hipStream_t s) {
-  ShtPlan& p = get_plan(g, L, s);
-  LegArgs la = leg_args(g, p);
-  la.skip = skip;
-  const LegChoice c = r.choice.at(std::make_pair(g, L));
-  const int64_t pst = (int64_t)g->nring * (L + 1);
-  {
-    ProfScope ps(FAM_LEG_SYNTH, leg_work(p, nm), s);
-    launch_leg_synth(c, la, nm, hat, nalm_of(L), r.phase.p, pst, s);
-  }
-  {
-    ProfScope ps(FAM_RING, bytes_work(ring_bytes(g, L, nm, RING_SYNTH)), s);
-    launch_ring(g, L, RING_SYNTH, nm, r.phase.p, pst, nullptr, map, g->npix, nullptr, 1, s, skip);
-  }
+  scratch_synth(r.sc, g, L, nm, hat, map, skip, s);
 }
 
-// adjoint transform of nm maps to per-tile partial sums in r.parts; returns the tile count
 int adjoint_ws(crs_grid g, int L, int nm, const double* map, MaskRun& r, MapSkip skip, hipStream_t s) {
-  ShtPlan& p = get_plan(g, L, s);
-  LegArgs la = leg_args(g, p);
-  la.skip = skip;
-  const LegChoice c = r.choice.at(std::make_pair(g, L));
-  const int nt = leg_adjoint_tiles(c, p.npairs, false);
-  const int64_t pst = (int64_t)g->nring * (L + 1);
-  {
-    ProfScope ps(FAM_RING, bytes_work(ring_bytes(g, L, nm, RING_ADJOINT)), s);
-    launch_ring(g, L, RING_ADJOINT, nm, r.phase.p, pst, map, nullptr, g->npix, nullptr, 1, s, skip);
-  }
-  {
-    ProfScope ps(FAM_LEG_ADJ, leg_work(p, nm), s);
-    launch_leg_adjoint(c, la, nm, r.phase.p, pst, r.parts.p, nalm_of(L), (int64_t)nm * nalm_of(L), false, s);
-  }
-  return nt;
+  return scratch_adjoint(r.sc, g, L, nm, map, skip, s);
 }
 
 void map_op(int op, MaskRun& r, double* x, const double* b, const double* y, const double* ind, const double* sm,
             double alpha, int64_t npix, MapSkip skip, hipStream_t s) {
-  hipLaunchKernelGGL(k_map_op, map_grid(npix, r.nm), dim3(256), 0, s, op, x, b, y, ind, sm, alpha, npix, skip);
-  CRS_HIP(hipGetLastError());
+  launch_map_op(op, x, b, y, ind, sm, alpha, npix, r.nm, skip, s);
 }
 
 void vcycle(const MaskMG& mg, MaskRun& r, int h, MapSkip skip, hipStream_t s) {
@@ -315,42 +196,42 @@ void vcycle(const MaskMG& mg, MaskRun& r, int h, MapSkip skip, hipStream_t s) {
   map_op(MOP_SCALE, r, r.x[h].p, r.b[h].p, nullptr, nullptr, r.sm[h].p, 0.0, np, skip, s);
   // u = Y_h^T x                                               (L_h, N_h)
   int nt = adjoint_ws(lv.grid, Lh, nm, r.x[h].p, r, skip, s);
-  hipLaunchKernelGGL(k_from_parts, alm_grid(Lh, nm), dim3(256), 0, s, r.u[h].p, (const int64_t*)nullptr, Lh, 0, 1.0,
-                     ph.hs.p, r.parts.p, nt, (int64_t)nm * nalm_of(Lh), (const double*)nullptr, 0,
-                     (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, skip);
+  launch_from_parts(r.u[h].p, (const int64_t*)nullptr, Lh, 0, 1.0,
+                     ph.hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(Lh), (const double*)nullptr, 0,
+                     (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, nm, skip, s);
   // r~ = W_h Y_h^T b - D_h u, at L_H                        (L_H, N_h)
   nt = adjoint_ws(lv.grid, LH, nm, r.b[h].p, r, skip, s);
   {
-    hipLaunchKernelGGL(k_from_parts, alm_grid(LH, nm), dim3(256), 0, s, r.rt[h].p, (const int64_t*)nullptr, LH, 0,
-                       lv.w, pH.hs.p, r.parts.p, nt, (int64_t)nm * nalm_of(LH), (const double*)nullptr, 0, r.u[h].p, Lh,
-                       nalm_of(Lh), lv.D.p, Lh + 1, r.mc.p, skip);
+    launch_from_parts(r.rt[h].p, (const int64_t*)nullptr, LH, 0,
+                       lv.w, pH.hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(LH), (const double*)nullptr, 0, r.u[h].p, Lh,
+                       nalm_of(Lh), lv.D.p, Lh + 1, r.mc.p, nm, skip, s);
   }
   // r_H = (mask_H) Y_H R_H r~                                (L_H, N_H)
-  hipLaunchKernelGGL(k_hat_from, alm_grid(LH, nm), dim3(256), 0, s, r.hat.p, LH, get_plan(cv.grid, LH, s).hs.p,
+  launch_hat_from(r.sc.hat.p, LH, get_plan(cv.grid, LH, s).hs.p,
                      (const double*)r.rt[h].p, LH, (const int64_t*)nullptr, nalm_of(LH), (const double*)nullptr, 0,
-                     (int64_t)0, lv.rH.p, 0, r.mc.p, skip);
+                     (int64_t)0, lv.rH.p, 0, r.mc.p, nm, skip, s);
   CRS_HIP(hipGetLastError());
-  synth_ws(cv.grid, LH, nm, r.hat.p, r.b[h + 1].p, r, skip, s);
+  synth_ws(cv.grid, LH, nm, r.sc.hat.p, r.b[h + 1].p, r, skip, s);
   map_op(MOP_MASK, r, r.b[h + 1].p, nullptr, nullptr, cv.ind.p, nullptr, 0.0, cv.grid->npix, skip, s);
   vcycle(mg, r, h + 1, skip, s);
   // c~ = R_H Y_H^T c_H                                       (L_H, N_H)
   nt = adjoint_ws(cv.grid, LH, nm, r.x[h + 1].p, r, skip, s);
-  hipLaunchKernelGGL(k_from_parts, alm_grid(LH, nm), dim3(256), 0, s, r.ct[h].p, (const int64_t*)nullptr, LH, 0,
-                     1.0, get_plan(cv.grid, LH, s).hs.p, r.parts.p, nt, (int64_t)nm * nalm_of(LH), lv.rH.p, 0,
-                     (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, skip);
+  launch_from_parts(r.ct[h].p, (const int64_t*)nullptr, LH, 0,
+                     1.0, get_plan(cv.grid, LH, s).hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(LH), lv.rH.p, 0,
+                     (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, nm, skip, s);
   // x += (mask_h) W_h Y_h c~                                 (L_H, N_h)
-  hipLaunchKernelGGL(k_hat_from, alm_grid(LH, nm), dim3(256), 0, s, r.hat.p, LH, pH.hs.p, (const double*)r.ct[h].p,
+  launch_hat_from(r.sc.hat.p, LH, pH.hs.p, (const double*)r.ct[h].p,
                      LH, (const int64_t*)nullptr, nalm_of(LH), (const double*)nullptr, 0, (int64_t)0,
-                     (const double*)nullptr, 0, r.mc.p, skip);
+                     (const double*)nullptr, 0, r.mc.p, nm, skip, s);
   CRS_HIP(hipGetLastError());
-  synth_ws(lv.grid, LH, nm, r.hat.p, r.y[h].p, r, skip, s);
+  synth_ws(lv.grid, LH, nm, r.sc.hat.p, r.y[h].p, r, skip, s);
   map_op(MOP_AXPY_MASK, r, r.x[h].p, nullptr, r.y[h].p, lv.ind.p, nullptr, lv.w, np, skip, s);
   // x += M_h (b - (mask_h) Y_h D_h (u + c~))                 (L_h, N_h)
-  hipLaunchKernelGGL(k_hat_from, alm_grid(Lh, nm), dim3(256), 0, s, r.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p,
+  launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p,
                      Lh, (const int64_t*)nullptr, nalm_of(Lh), (const double*)r.ct[h].p, LH, nalm_of(LH), lv.D.p,
-                     Lh + 1, r.mc.p, skip);
+                     Lh + 1, r.mc.p, nm, skip, s);
   CRS_HIP(hipGetLastError());
-  synth_ws(lv.grid, Lh, nm, r.hat.p, r.y[h].p, r, skip, s);
+  synth_ws(lv.grid, Lh, nm, r.sc.hat.p, r.y[h].p, r, skip, s);
   map_op(MOP_POST, r, r.x[h].p, r.b[h].p, r.y[h].p, lv.ind.p, r.sm[h].p, 0.0, np, skip, s);
 }
 
@@ -564,7 +445,6 @@ MaskRun& mask_run(Exec& e, int p, hipStream_t s) {
   r->rt.resize(nl);
   r->ct.resize(nl);
   r->sm.resize(nl);
-  size_t maxhat = 0, maxph = 0, maxparts = 0;
   for (int h = 0; h < nl; ++h) {
     const MaskLevel& lv = mg.levels[h];
     const size_t np = (size_t)lv.grid->npix * r->nm;
@@ -581,18 +461,8 @@ MaskRun& mask_run(Exec& e, int p, hipStream_t s) {
       r->rt[h].alloc((size_t)nalm_of(Ls[1]) * r->nm);
       r->ct[h].alloc((size_t)nalm_of(Ls[1]) * r->nm);
     }
-    for (int L : Ls) {
-      ShtPlan& pl = get_plan(lv.grid, L, s);
-      const LegChoice c = leg_choice(pl.npairs, L, r->nm);
-      r->choice[std::make_pair(lv.grid, L)] = c;
-      maxhat = std::max(maxhat, (size_t)nalm_of(L) * r->nm);
-      maxph = std::max(maxph, (size_t)lv.grid->nring * (L + 1) * r->nm);
-      maxparts = std::max(maxparts, (size_t)leg_adjoint_tiles(c, pl.npairs, false) * nalm_of(L) * r->nm);
-    }
+    for (int L : Ls) r->sc.reserve(lv.grid, L, r->nm, s);
   }
-  r->hat.alloc(maxhat);
-  r->phase.alloc(maxph);
-  r->parts.alloc(maxparts);
   CRS_HIP(hipStreamSynchronize(s));
   slot = std::move(r);
   return *slot;
@@ -618,17 +488,17 @@ void exec_mask(Exec& e, const double* r, double* z, bool accumulate, hipStream_t
     const int L0 = mg.L0;
     const ShtPlan& p0 = get_plan(l0.grid, L0, s);
     // b_0 = (mask) Y R r_k
-    hipLaunchKernelGGL(k_hat_from, alm_grid(L0, run.nm), dim3(256), 0, s, run.hat.p, L0, p0.hs.p, r, L0,
-                       run.off_top.p, (int64_t)0, (const double*)nullptr, 0, (int64_t)0, mg.rtop.p, 0, run.mc.p, skip);
+    launch_hat_from(run.sc.hat.p, L0, p0.hs.p, r, L0,
+                       run.off_top.p, (int64_t)0, (const double*)nullptr, 0, (int64_t)0, mg.rtop.p, 0, run.mc.p, run.nm, skip, s);
     CRS_HIP(hipGetLastError());
-    synth_ws(l0.grid, L0, run.nm, run.hat.p, run.b[0].p, run, skip, s);
+    synth_ws(l0.grid, L0, run.nm, run.sc.hat.p, run.b[0].p, run, skip, s);
     map_op(MOP_MASK, run, run.b[0].p, nullptr, nullptr, l0.ind.p, nullptr, 0.0, l0.grid->npix, skip, s);
     vcycle(mg, run, 0, skip, s);
     // z_k (+)= R Y^T x_0
     const int nt = adjoint_ws(l0.grid, L0, run.nm, run.x[0].p, run, skip, s);
-    hipLaunchKernelGGL(k_from_parts, alm_grid(L0, run.nm), dim3(256), 0, s, z, run.off_top.p, L0, accumulate ? 1 : 0,
-                       1.0, p0.hs.p, run.parts.p, nt, (int64_t)run.nm * nalm_of(L0), mg.rtop.p, 0,
-                       (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, run.mc.p, skip);
+    launch_from_parts(z, run.off_top.p, L0, accumulate ? 1 : 0,
+                       1.0, p0.hs.p, run.sc.parts.p, nt, (int64_t)run.nm * nalm_of(L0), mg.rtop.p, 0,
+                       (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, run.mc.p, run.nm, skip, s);
     CRS_HIP(hipGetLastError());
   }
 }

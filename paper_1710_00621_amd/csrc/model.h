@@ -50,6 +50,19 @@ constexpr int kWorkBlock = 256;
 // per band of a problem in an Exec: {L, group maps, map base, tiles, map stride, dropped from M_PI}
 constexpr int kBinfo = 6;
 
+// One spatially varying mixing pair (band nu, component k), eq:Q:
+// Q~ = Y^T W Q Y on its grid at the component band-limit.
+struct VarMix {
+  int nu = 0, k = 0;
+  crs_grid grid = nullptr;   // not owned
+  DevBuf<double> qw;         // q(n_i) w_i per pixel
+  double qeff = 0.0;         // eq:optimal-q, the preconditioners' scalar
+};
+struct VarMixRun;
+struct VarMixRunDel {
+  void operator()(VarMixRun* p) const;
+};
+
 struct Band {
   crs_grid grid = nullptr;
   int lmax = 0;
@@ -79,7 +92,12 @@ struct ProbDev {
   const double* ftab;    // f_lm triangle at Lf
   const double* Dinv;    // [(Lc+1)^2][nc][nc] M_diag blocks (NULL without)
   const double* const* vptr;  // per band: partial sums of its group (this Exec)
-  const int* binfo;           // per band: {L, group maps, map base, tiles, map stride}
+  const int* binfo;           // per band: {L, group maps, map base, tiles, map stride, dropped from M_PI}
+  // spatially varying mixing (eq:Q): per (band, component) the pair's index
+  // or -1 (NULL: none); y_v = Q~ x_k per system at ybuf + yoff[v] + rhs nalm(L_k)
+  const int* vidx;
+  const double* ybuf;
+  const int64_t* yoff;
 };
 struct SysDev {
   int prob, rhs;
@@ -109,6 +127,36 @@ struct ExecGroup {
   DevBuf<const double*> dptr, wptr;   // per map: data / omega_1 maps (right-hand side)
 };
 
+// ------------------------------------------- harmonic / map batch operations
+// (harmonic.hip).  nm vectors or maps per launch, map j skipped when skip.off(j).
+// out_hat[j] = hs f_j[l] (in1_j + in2_j) repacked to LO (in1_j at in1 + off1[j]
+// or + j st1; in2 optional at in2 + j st2; f_j = F + mc[j] fst, optional)
+void launch_hat_from(double* out, int LO, const double* hs, const double* in1, int L1, const int64_t* off1,
+                     int64_t st1, const double* in2, int L2, int64_t st2, const double* F, int fst, const int* mc,
+                     int nm, MapSkip skip, hipStream_t s);
+// out_j (at out + offo[j] or + j nalm(LO)) (+)= alpha f_j[l] hs sum_t parts[t][j] - g_j[l] sub_j
+void launch_from_parts(double* out, const int64_t* offo, int LO, int acc, double alpha, const double* hs,
+                       const double* parts, int ntiles, int64_t tstride, const double* F, int fst, const double* sub,
+                       int Ls, int64_t sst, const double* Gs, int gst, const int* mc, int nm, MapSkip skip,
+                       hipStream_t s);
+enum { MOP_MASK = 0, MOP_SCALE = 1, MOP_AXPY_MASK = 2, MOP_POST = 3, MOP_ZERO = 4 };
+// MASK: x *= ind; SCALE: x = sm_j b; AXPY_MASK: x += alpha ind y; POST: x += sm_j (b - ind y); ZERO: x = 0
+void launch_map_op(int op, double* x, const double* b, const double* y, const double* ind, const double* sm,
+                   double alpha, int64_t npix, int nm, MapSkip skip, hipStream_t s);
+// Transform scratch sized by reserve() for every (grid, L, maps) it will run;
+// the Legendre kernel choice of a (grid, L) is fixed at its first reserve.
+struct ShtScratch {
+  DevBuf<double> hat, parts;
+  DevBuf<double2> phase;
+  std::map<std::pair<crs_grid, int>, std::pair<int, LegChoice>> choice;
+  void reserve(crs_grid g, int L, int nm, hipStream_t s);
+};
+// map[j] = Y hat[j] (hat: nm x nalm(L) hat vectors; map stride npix)
+void scratch_synth(ShtScratch& w, crs_grid g, int L, int nm, const double* hat, double* map, MapSkip skip,
+                   hipStream_t s);
+// Y^T map to per-tile partial sums in w.parts ([tile][j][nalm(L)]); returns the tile count
+int scratch_adjoint(ShtScratch& w, crs_grid g, int L, int nm, const double* map, MapSkip skip, hipStream_t s);
+
 // Mask-restricted preconditioner (mask.hip): the multigrid hierarchy of a
 // model and the per-Exec state of its cycle.
 struct MaskMG;
@@ -137,6 +185,7 @@ struct Exec {
   std::vector<ExecGroup> groups;
   DevBuf<ProbDev> dprobs;
   DevBuf<SysDev> dsys;
+  DevBuf<int> sys_ident;          // 0 .. nsys-1 (per-system map skipping)
   DevBuf<int2> rows;              // (system, component) rows of the back-mix
   int nrows = 0;
   DevBuf<int4> wl_rows;           // work list over rows: (row, first, end) per block
@@ -175,6 +224,10 @@ struct Exec {
   hipStream_t cap_stream = nullptr;
   ExecStats stats;                // of the last exec_pcg
   std::vector<std::unique_ptr<MaskRun, MaskRunDel>> mask_runs;  // per problem (M_mask)
+  std::unique_ptr<VarMixRun, VarMixRunDel> varmix;             // spatially varying mixing
+  const int* vm_vidx = nullptr;                                // its device tables (in varmix)
+  const double* vm_ybuf = nullptr;
+  const int64_t* vm_yoff = nullptr;
   ~Exec();
 };
 
@@ -233,6 +286,20 @@ void exec_mask(Exec& e, const double* r, double* z, bool accumulate, hipStream_t
 bool exec_has_mask(const Exec& e);
 // allocates the cycle state of every masked problem of e (before any capture)
 void exec_mask_prepare(Exec& e, hipStream_t s);
+// Spatially varying mixing (mixmap.hip): y_v = Q~_v x_k of every pair for
+// every system (before the forward mix), and out_k += Q~_v (B_nu v_nu) of
+// every pair after the transpose mix (v_nu: the band adjoints in the group
+// partial sums).  No-ops without mixing maps.
+void exec_varmix_fwd(Exec& e, const double* x, hipStream_t s, const double* act);
+void exec_varmix_back(Exec& e, double* out, hipStream_t s, const double* act);
+bool exec_has_varmix(const Exec& e);
+void exec_varmix_prepare(Exec& e, hipStream_t s);
+// mixing scalar of (band, component) for the A tables (1 for a varying pair,
+// whose map acts through Q~) and for the preconditioners (eq:optimal-q)
+double mix_q_a(crs_model m, int nu, int k);
+double mix_q_pre(crs_model m, int nu, int k);
+// rebuilds the mixing, U^+ and M_diag tables and drops the model's Execs
+void model_rebuild_tables(crs_model m, hipStream_t s);
 // the model's Exec for nrhs right-hand sides (built on first use)
 Exec& model_exec_ref(crs_model m, int nrhs, hipStream_t s);
 
@@ -267,6 +334,7 @@ struct crs_model_s {
   std::map<int, std::unique_ptr<crs::Exec>> execs;
   crs::DevBuf<double> om1, om2, bcr;
   std::unique_ptr<crs::MaskMG, crs::MaskMGDel> mask;  // M_mask hierarchy (crs_model_set_mask)
+  std::vector<crs::VarMix> varmix;   // spatially varying mixing pairs (eq:Q)
   std::vector<int> merge_group;      // per band: observation-merge group (-1: alone), App. A.3
   std::vector<char> pi_drop;         // per band: merged into another band's row of U (no T^+)
   int device = 0;

@@ -152,7 +152,7 @@ void build_pinv_tables(crs_model m, hipStream_t s) {
       const int k = act[ja];
       for (int nu = 0; nu < nb; ++nu)
         if (l <= m->bands[nu].lmax)
-          U[(size_t)nu * na + ja] = std::sqrt(m->bands[nu].alpha2) * m->bands[nu].beam[l] * m->bands[nu].q[k];
+          U[(size_t)nu * na + ja] = std::sqrt(m->bands[nu].alpha2) * m->bands[nu].beam[l] * mix_q_pre(m, nu, k);
       U[(size_t)(nb + k) * na + ja] = std::sqrt(m->invcl[k][l]);
     }
     // merged observations (App. A.3): per group the representative's row
@@ -202,7 +202,7 @@ void build_mix_tables(crs_model m, hipStream_t s) {
     for (int nu = 0; nu < nb; ++nu)
       if (l <= m->bands[nu].lmax) {
         bt[(size_t)l * nb + nu] = m->bands[nu].beam[l];
-        for (int k = 0; k < nc; ++k) cA[((size_t)l * nb + nu) * nc + k] = m->bands[nu].beam[l] * m->bands[nu].q[k];
+        for (int k = 0; k < nc; ++k) cA[((size_t)l * nb + nu) * nc + k] = m->bands[nu].beam[l] * mix_q_a(m, nu, k);
       }
     for (int k = 0; k < nc; ++k)
       if (l <= m->lk[k]) {
@@ -259,7 +259,7 @@ void build_diag(crs_model m, hipStream_t s) {
           if (l > b.lmax) continue;
           const double d = dg[nu][moff_h(b.lmax, mm) + (int64_t)part * (b.lmax - mm + 1) + (l - mm)] * b.beam[l] * b.beam[l];
           for (int i = 0; i < na; ++i)
-            for (int j = 0; j < na; ++j) Da[i * na + j] += d * b.q[act[i]] * b.q[act[j]];
+            for (int j = 0; j < na; ++j) Da[i * na + j] += d * mix_q_pre(m, nu, act[i]) * mix_q_pre(m, nu, act[j]);
         }
         for (int i = 0; i < na; ++i) Da[i * na + i] += m->invcl[act[i]][l];
         // inverse of the symmetric block (pseudo-inverse if singular)
@@ -330,6 +330,27 @@ std::vector<std::vector<const double*>> sys_band_ptrs(crs_model m, int nrhs, con
 
 namespace crs {
 Exec& model_exec_ref(crs_model m, int nrhs, hipStream_t s) { return model_exec(m, nrhs, s); }
+
+double mix_q_a(crs_model m, int nu, int k) {
+  for (const VarMix& v : m->varmix)
+    if (v.nu == nu && v.k == k) return 1.0;
+  return m->bands[nu].q[k];
+}
+
+double mix_q_pre(crs_model m, int nu, int k) {
+  for (const VarMix& v : m->varmix)
+    if (v.nu == nu && v.k == k) return v.qeff;
+  return m->bands[nu].q[k];
+}
+
+void model_rebuild_tables(crs_model m, hipStream_t s) {
+  CRS_HIP(hipStreamSynchronize(s));
+  build_mix_tables(m, s);
+  build_pinv_tables(m, s);
+  if (m->has_diag) build_diag(m, s);
+  m->execs.clear();
+  CRS_HIP(hipStreamSynchronize(s));
+}
 
 void launch_philox_normals(uint64_t seed, uint64_t stream, uint64_t rhs0, int nrhs, int64_t n, double* out,
                            hipStream_t s) {
@@ -568,6 +589,7 @@ int apply_prior_inv(crs_model m, int nrhs, const double* x, double* y, crs_strea
 int apply_dA_dmix(crs_model m, int nrhs, const double* lam, const double* x, double* dq, crs_stream st) {
   return guarded([&] {
     check_vec(m, nrhs, lam, x);
+    CRS_CHECK(m->varmix.empty(), CRS_EUNSUPPORTED, "mixing gradients with spatially varying mixing maps");
     CRS_CHECK(dq != nullptr, CRS_EINVAL, "dq is NULL");
     hipStream_t s = (hipStream_t)st;
     // systems [x_0 .. x_{nrhs-1}, lam_0 .. lam_{nrhs-1}] through the band round trips
@@ -586,6 +608,7 @@ int apply_dA_dmix(crs_model m, int nrhs, const double* lam, const double* x, dou
 int apply_db_dmix(crs_model m, int nrhs, const double* lam, const double* const* d, double* dq, crs_stream st) {
   return guarded([&] {
     check_vec(m, nrhs, lam, dq);
+    CRS_CHECK(m->varmix.empty(), CRS_EUNSUPPORTED, "mixing gradients with spatially varying mixing maps");
     CRS_CHECK(d != nullptr, CRS_EINVAL, "d is NULL");
     hipStream_t s = (hipStream_t)st;
     Exec& e = model_exec(m, nrhs, s);

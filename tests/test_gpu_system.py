@@ -305,3 +305,77 @@ def test_merged_observations_match_oracle():
     assert ref.status == "ok" and info["status"] == 0
     assert _rel(xs.cpu().numpy(), ref.x) < SOL_TOL
     assert abs(info["iters"][0] - ref.iters) <= 2
+
+
+def _varmix_models(const=None, extra_pair=False):
+    """GPU and oracle copies of a two-band, two-component model whose
+    (band 1, component 1) mixing is a smooth map on a Gauss-Legendre grid
+    (const: a flat map); extra_pair adds a HEALPix mixing map on (band 0, comp 1)."""
+    torch, crsolve = _setup()
+    from oracle import geometry as ogeo
+    from oracle.model import Model as OModel
+    rng = np.random.default_rng(13)
+    L = 10
+    o8, o4 = ogeo.healpix(8), ogeo.healpix(4)
+    g8, g4 = crsolve.Grid.healpix(8), crsolve.Grid.healpix(4)
+    t8 = np.exp(0.4 * rng.standard_normal(o8.npix))
+    t4 = np.exp(0.4 * rng.standard_normal(o4.npix))
+    comps = [{"lmax": L, "invcl": inputs.inv_cl("cmb", L, amplitude=0.05)},
+             {"lmax": L, "invcl": inputs.inv_cl("powerlaw", L, amplitude=0.05)}]
+    q = np.array([[1.0, 0.8], [1.0, 1.7]])
+    spec = [(g8, o8, L, inputs.gaussian_beam(400.0, L), t8), (g4, o4, 8, inputs.gaussian_beam(600.0, 8), t4)]
+    oq = ogeo.gauss_legendre(L + 1, 2 * L + 1)
+    gq = crsolve.Grid.gauss_legendre(L + 1, 2 * L + 1)
+    z, phi = oq.pixel_centres()
+    qmap = np.full(oq.npix, const) if const is not None else \
+        1.7 * (1.0 + 0.3 * z + 0.2 * np.cos(phi) * (1 - z * z))
+    maps = {(1, 1): (oq, qmap)}
+    gm = crsolve.Model([{"grid": g, "lmax": l, "beam": b, "tau": t} for g, _, l, b, t in spec], comps, q, diag=True)
+    gm.set_mixing_map(1, 1, gq, qmap)
+    if extra_pair:
+        z8, phi8 = o8.pixel_centres()
+        q8 = 0.8 * (1.0 - 0.25 * z8 * z8)
+        maps[(0, 1)] = (o8, q8)
+        gm.set_mixing_map(0, 1, g8, q8)
+    om = OModel([{"grid": o, "lmax": l, "beam": b, "tau": t} for _, o, l, b, t in spec], comps, q, mixing_maps=maps)
+    gm._keep_grids = (g8, g4, gq)
+    return om, gm
+
+
+@pytest.mark.parametrize("extra", [False, True])
+def test_varying_mixing_maps_match_oracle(extra):
+    """eq:Q on the GPU: A, the right-hand side, P x and both preconditioners
+    (with the eq:optimal-q scalar) against the oracle element by element, and
+    a PCG solve to 1e-12; a flat map equals scalar mixing."""
+    torch, crsolve = _setup()
+    om, gm = _varmix_models(extra_pair=extra)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, om.n))
+    xt = torch.tensor(x, device="cuda")
+    y = gm.apply_A(xt).cpu().numpy()
+    zp = gm.apply_pinv(xt).cpu().numpy()
+    zd = gm.apply_diag(xt).cpu().numpy()
+    Mp, Md = precond.PseudoInversePrecond(om), precond.DiagonalPrecond(om)
+    for i in range(2):
+        assert _rel(y[i], om.apply_A(x[i])) < OP_TOL
+        assert _rel(zp[i], Mp(x[i])) < OP_TOL
+        assert _rel(zd[i], Md(x[i])) < OP_TOL
+    maps = gm.project(xt[0])
+    for nu in range(2):
+        assert _rel(maps[nu].cpu().numpy(), om.project(x[0], nu)) < OP_TOL
+    d = [rng.standard_normal(b["grid"].npix) for b in om.bands]
+    b = gm.build_rhs(d=[torch.tensor(v, device="cuda").unsqueeze(0) for v in d])[0].cpu().numpy()
+    bref = rhs.build_rhs(om, d=d)
+    assert _rel(b, bref) < OP_TOL
+    ref = pcg.pcg(om.apply_A, Mp, bref, rtol=1e-12, maxiter=500)
+    xs, info = gm.pcg(torch.tensor(bref, device="cuda"), precond="pinv", rtol=1e-12, maxiter=500)
+    assert ref.status == "ok" and info["status"] == 0
+    assert _rel(xs.cpu().numpy(), ref.x) < SOL_TOL
+    assert abs(info["iters"][0] - ref.iters) <= 2
+    if not extra:
+        om_c, gm_c = _varmix_models(const=1.7)
+        scal = crsolve.Model([{"grid": g, "lmax": l, "beam": bb, "tau": t}
+                              for g, (l, bb, t) in zip(gm_c._keep_grids[:2],
+                                                       [(b_["lmax"], b_["beam"], b_["tau"]) for b_ in om_c.bands])],
+                             om_c.comps, om_c.q, diag=False)
+        assert _rel(gm_c.apply_A(xt).cpu().numpy(), scal.apply_A(xt).cpu().numpy()) < 1e-12
