@@ -191,7 +191,7 @@ def cpu_baseline(name, probs, gpu_iters, precond, budget_s=20.0):
 
     nthreads = _blas_threads()
     if name != "batched":
-        scale = 8 if name == "masked" else 2
+        scale = {"masked": 8, "fullres": 16}.get(name, 2)
         prob = inputs.make_problem(name, scale=scale)
         cache = {}
 
@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "multires", "masked"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "multires", "masked", "fullres"])
     ap.add_argument("--nprob", type=int, default=64)
     ap.add_argument("--precond", default=None, choices=["pinv", "diag", "add"])
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -365,6 +365,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t0 = time.time()
+    free0 = torch.cuda.mem_get_info(dev)[0]
     probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
@@ -465,6 +466,11 @@ def main():
                 "note": "pseudo-inverse preconditioner under a mask (tau^+ = 0 there), maxiter 3000"}
             log(f"pinv sample: {extra['pinv_sample']}")
     elif a.workload != "batched":
+        if a.workload == "fullres":
+            # memory plan of the single large model: tables and operator state,
+            # against the device memory the run actually took
+            mb, eb = probs[0]["model"].plan_bytes(1)
+            extra["memory"] = {"model_tables_GiB": mb / 2 ** 30, "operator_state_GiB": eb / 2 ** 30}
         # the masked workload may stop at maxiter above rtol (reported, not an error)
         nc = a.workload == "masked"
         for w in range(a.warmup):
@@ -490,6 +496,11 @@ def main():
             extra["ms_per_iteration"] = ms_per_step / max(1, sum(iters))
             log(f"not converged to {a.rtol} in {a.maxiter} iterations: relres {extra['final_relres']}")
         log(f"timed {a.steps} steps: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
+        if a.workload == "fullres":
+            torch.cuda.synchronize()
+            extra["memory"]["device_used_GiB"] = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2 ** 30
+            extra["memory"]["device_total_GiB"] = torch.cuda.mem_get_info(dev)[1] / 2 ** 30
+            log(f"memory: {extra['memory']}")
         if a.workload == "masked":
             # the other preconditioners for five times as many iterations (they
             # do not reach rtol under the mask): residual reached and time per iteration

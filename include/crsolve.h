@@ -178,6 +178,14 @@ int crs_model_create(const crs_model_desc* d, crs_stream s, crs_model* out);
 int crs_model_destroy(crs_model m);
 /* n = sum_k (L_k+1)^2 */
 int crs_model_size(crs_model m, int64_t* n);
+/* Memory plan (host computation, nothing allocated): the model's own
+ * device tables (model_bytes) and the operator / solver state for nrhs
+ * right-hand sides (exec_bytes: per (grid, L) group the harmonic inputs,
+ * phase array, adjoint partial sums and pixel maps, plus the PCG vectors).
+ * The first operator call with a new nrhs allocates exec_bytes; it returns
+ * CRS_ENOMEM before allocating anything if they exceed the free device
+ * memory.  Either pointer may be NULL. */
+int crs_model_plan_bytes(crs_model m, int nrhs, int64_t* model_bytes, int64_t* exec_bytes);
 /* alpha_nu^2 for every band (host array of nbands). */
 int crs_model_alpha2(crs_model m, double* alpha2);
 /* Replace the mixing matrix q (host, nbands x ncomp, row = band) and

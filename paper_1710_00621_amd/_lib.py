@@ -73,6 +73,7 @@ _SIGS = {
     "crs_model_destroy": (ctypes.c_int, [vp]),
     "crs_model_size": (ctypes.c_int, [vp, c_int64_p]),
     "crs_model_alpha2": (ctypes.c_int, [vp, c_double_p]),
+    "crs_model_plan_bytes": (ctypes.c_int, [vp, ctypes.c_int, c_int64_p, c_int64_p]),
     "crs_model_set_mixing": (ctypes.c_int, [vp, c_double_p, vp]),
     "crs_model_set_mixing_map": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, c_double_p, vp]),
     "crs_model_merge_observations": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), vp]),

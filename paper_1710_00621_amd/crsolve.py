@@ -203,6 +203,12 @@ class Model:
         except Exception:
             pass
 
+    def plan_bytes(self, nrhs=1):
+        """(model tables, operator state for nrhs right-hand sides) in bytes."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().crs_model_plan_bytes(self._h, int(nrhs), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def alpha2(self):
         a = np.empty(self.nbands)
         check(lib().crs_model_alpha2(self._h, a.ctypes.data_as(c_double_p)))

@@ -557,8 +557,45 @@ Exec::~Exec() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
+int64_t exec_plan_bytes(const std::vector<crs_model>& models, int nrhs) {
+  // the buffers make_exec allocates (the right-hand side's pixel maps are
+  // allocated on the first build_rhs / project and counted here too)
+  std::map<std::pair<crs_grid, int>, int> maps;
+  int64_t ntot = 0, nsys = 0;
+  for (const crs_model m : models) {
+    ntot += m->n * nrhs;
+    nsys += nrhs;
+    for (const Band& b : m->bands) maps[std::make_pair(b.grid, b.lmax)] += nrhs;
+  }
+  int64_t bytes = 0;
+  for (const auto& kv : maps) {
+    const crs_grid g = kv.first.first;
+    const int L = kv.first.second, nm = kv.second;
+    const int64_t nalm = (int64_t)(L + 1) * (L + 1);
+    const int npairs = (g->nring + 1) / 2;
+    const LegChoice c = leg_choice(npairs, L, nm);
+    bytes += (int64_t)nm * nalm * 8;                          // uhat
+    bytes += (int64_t)nm * g->nring * (L + 1) * 16;           // phase
+    bytes += (int64_t)leg_adjoint_tiles(c, npairs, false) * nm * nalm * 8;  // adjoint partial sums
+    bytes += (int64_t)nm * g->npix * 8;                       // pixel maps (right-hand side)
+  }
+  bytes += 7 * ntot * 8;                                      // r, z, p, q, t, x and the caller's b
+  bytes += nsys * (kDotBlocks + 4 * kScal) * 8;
+  return bytes;
+}
+
 std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s, bool autotune) {
   CRS_CHECK(!models.empty() && nrhs >= 1, CRS_EINVAL, "no systems");
+  {
+    // memory plan: refuse up front rather than fail part-way through the allocations
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) == hipSuccess) {
+      const int64_t need = exec_plan_bytes(models, nrhs);
+      CRS_CHECK(need <= (int64_t)freeb, CRS_ENOMEM,
+                "the operator state needs " + std::to_string(need >> 20) + " MiB of device memory, " +
+                    std::to_string(freeb >> 20) + " MiB are free");
+    }
+  }
   auto e = std::make_unique<Exec>();
   e->probs = models;
   const int np = (int)models.size();

@@ -237,6 +237,8 @@ struct Exec {
 // (leg_autotune) instead of taking the default rules.
 std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, hipStream_t s,
                                 bool autotune = false);
+// device bytes make_exec allocates for these models and right-hand-side count
+int64_t exec_plan_bytes(const std::vector<crs_model>& models, int nrhs);
 
 enum OpKind { OP_A = 0, OP_PI = 1 };
 // act: per-system flags at stride 8 (the PCG scalars' active slot, or the

@@ -468,6 +468,23 @@ int crs_model_size(crs_model m, int64_t* n) {
   });
 }
 
+int crs_model_plan_bytes(crs_model m, int nrhs, int64_t* model_bytes, int64_t* exec_bytes) {
+  return guarded([&] {
+    CRS_CHECK(m != nullptr && nrhs >= 1, CRS_EINVAL, "model is NULL or nrhs < 1");
+    if (model_bytes) {
+      int64_t b = 0;
+      const int64_t nl = m->Lmax + 1;
+      b += 4 * nl * m->nbands * m->ncomp * 8;                             // mixing and U^+ tables
+      b += 3 * nl * m->ncomp * 8 + nl * m->ncomp * m->ncomp * 8;          // prior terms
+      if (m->has_diag) b += (int64_t)(m->Lc + 1) * (m->Lc + 1) * m->ncomp * m->ncomp * 8;  // M_diag
+      for (const Band& bd : m->bands) b += 2 * bd.npix * 8;               // tau and T^+ weights
+      *model_bytes = b;
+    }
+    if (exec_bytes) *exec_bytes = exec_plan_bytes({m}, nrhs);
+    return CRS_OK;
+  });
+}
+
 int crs_model_alpha2(crs_model m, double* a2) {
   return guarded([&] {
     CRS_CHECK(m != nullptr && a2 != nullptr, CRS_EINVAL, "model or alpha2 is NULL");

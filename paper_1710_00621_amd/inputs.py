@@ -24,6 +24,9 @@ Sect. 5):
             1-3 components, sky fraction ~ U[0.6, 0.95].
   diff      7 bands 30..353 GHz at Nside 256, L = 512, FWHM 37.5', RMS ~
             U[0.5, 1.5], CMB + synchrotron + dust, full sky.
+  fullres   the masked recipe's 9 bands and components at full Planck-like
+            resolution: Nside 1024 (x3) / 2048 (x6), L_nu = min(6000, 2
+            Nside), L_k = 6000, full sky, Wiener filter.
 Every recipe also has a ``scale`` knob that divides Nside and every
 band-limit (and multiplies the FWHM) to give small copies for the oracle.
 
@@ -144,6 +147,17 @@ def make_problem(name, scale=1, index=0):
         return _problem(bands, comps, ("lognormal", 0.3),
                         ("galactic_disks", math.sin(math.radians(15.0)), 500), 3, name,
                         rhs="cr")
+    if name == "fullres":
+        fr = [30.0, 44.0, 70.0, 100.0, 143.0, 217.0, 353.0, 545.0, 857.0]
+        bands = []
+        for i, f in enumerate(fr):
+            n = (1024 if i < 3 else 2048) // s
+            bands.append({"freq": f, "grid": ("healpix", n),
+                          "lmax": min(6000 // s, 2 * n),
+                          "fwhm": 30.0 * (1.0 / 6.0) ** (i / 8.0) * s})
+        comps = [dict(CMB, lmax=6000 // s), dict(SYNC, lmax=6000 // s),
+                 dict(DUST, lmax=6000 // s)]
+        return _problem(bands, comps, ("lognormal", 0.3), None, 6, name)
     if name == "batched":
         i = int(index)
         nmax_full = (64, 128, 256)[i % 3]
