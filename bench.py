@@ -336,6 +336,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sht-roofline", action="store_true")
     ap.add_argument("--no-multires", action="store_true")
+    ap.add_argument("--group-streams", type=int, default=4,
+                    help="also time the batch with its transform groups on this many streams (1: skip)")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched workload: skip the plain (one solve per problem) pass and the "
                          "pseudo-inverse sample")
@@ -397,6 +399,23 @@ def main():
         log(f"batched: {ms_per_step:.1f} ms/step, {per_rhs:.3f} ms/RHS")
         gstats = batch.stats()
         extra["graphs"] = {**gstats, "iterations_per_launch": gstats["iterations"] / max(1, gstats["graph_launches"])}
+        if a.group_streams > 1:
+            # the same solves with the transform groups on several streams
+            # (outside the timed region, no profiling: concurrent kernels'
+            # event durations overlap, so the roofline above is taken with
+            # the groups serialized)
+            batch.set_streams(a.group_streams)
+            batch_solve(batch, probs, a.precond, a.rtol, a.maxiter)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            for k in range(a.steps):
+                batch_solve(batch, probs, a.precond, a.rtol, a.maxiter)
+            torch.cuda.synchronize()
+            conc_rhs = (time.perf_counter() - tc) * 1e3 / a.steps / nrhs
+            batch.set_streams(1)
+            log(f"batched, groups on {a.group_streams} streams: {conc_rhs:.3f} ms/RHS")
+            extra["concurrent_groups"] = {"streams": a.group_streams, "ms_per_RHS": conc_rhs,
+                                          "speedup": per_rhs / conc_rhs}
         mode = (f"batched: one stacked PCG over all {nrhs} problems in chunks of 8 iterations per "
                 f"captured hipGraph launch (convergence tested on the device, the host reading flags "
                 f"between chunks; finished transform groups left out)")

@@ -373,6 +373,15 @@ int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const 
  * slowest problem, graph launches, graphs captured, host reads of the PCG
  * flags. */
 int crs_batch_stats(crs_batch b, int* out);
+/* Runs the batch's transform groups (the bands sharing a grid and
+ * band-limit) on up to nstreams HIP streams (1..8; default 1, or the
+ * environment variable CRS_GROUP_STREAMS at creation): the groups of one
+ * operator application are independent until the back-mix (eq:A sums over
+ * bands), so their launches may overlap, forked from and joined back into the
+ * solve's stream by events (graph edges inside the captured chunks).  The
+ * extra streams have the default priority and are created here; results do
+ * not depend on nstreams.  CRS_EINVAL outside 1..8. */
+int crs_batch_set_streams(crs_batch b, int nstreams);
 
 /* ------------------------------------------------------------- profiling
  * With profiling on, every Legendre-stage kernel launch is bracketed by HIP

@@ -108,6 +108,7 @@ _SIGS = {
                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(vp), c_int_p,
                                        c_double_p, ctypes.c_int, vp]),
     "crs_batch_stats": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int)]),
+    "crs_batch_set_streams": (ctypes.c_int, [vp, ctypes.c_int]),
     "crs_philox_normals": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_int64, vp, vp]),
     "crs_set_profiling": (ctypes.c_int, [ctypes.c_int]),

@@ -475,6 +475,10 @@ class Batch:
             check(st)
         return xs, {"status": st, "iters": list(iters), "relres": list(rel)}
 
+    def set_streams(self, n):
+        """Run the transform groups on up to n HIP streams (1..8)."""
+        check(lib().crs_batch_set_streams(self._h, int(n)))
+
     def stats(self):
         """Counters of the last solve: iterations, graph_launches,
         graph_captures, host_syncs."""

@@ -108,6 +108,14 @@ int crs_batch_solve(crs_batch b, int mode, const double* const* const* d, const 
   });
 }
 
+int crs_batch_set_streams(crs_batch b, int nstreams) {
+  return guarded([&] {
+    CRS_CHECK(b != nullptr, CRS_EINVAL, "batch is NULL");
+    exec_set_streams(*b->ex, nstreams);
+    return CRS_OK;
+  });
+}
+
 int crs_batch_stats(crs_batch b, int* out) {
   return guarded([&] {
     CRS_CHECK(b != nullptr && out != nullptr, CRS_EINVAL, "batch or out is NULL");

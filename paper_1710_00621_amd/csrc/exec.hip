@@ -555,6 +555,9 @@ Exec::~Exec() {
   if (hscal) (void)hipHostFree(hscal);
   if (hsel) (void)hipHostFree(hsel);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  for (hipStream_t t : side) (void)hipStreamDestroy(t);
+  for (hipEvent_t ev : join) (void)hipEventDestroy(ev);
+  if (fork) (void)hipEventDestroy(fork);
 }
 
 int64_t exec_plan_bytes(const std::vector<crs_model>& models, int nrhs) {
@@ -783,6 +786,7 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
   e->hrows.alloc((size_t)kChunk * e->nsys);
   e->live.assign(e->groups.size(), 1);
   CRS_HIP(hipStreamSynchronize(s));
+  if (const char* v = std::getenv("CRS_GROUP_STREAMS")) exec_set_streams(*e, std::atoi(v));
   return e;
 }
 
@@ -811,12 +815,28 @@ Work3 group_work(const Exec& e, int gi, int family, bool masked, bool pi) {
   return leg_work(*g.plan, na);
 }
 
-void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act) {
+void exec_set_streams(Exec& e, int n) {
+  CRS_CHECK(n >= 1 && n <= kMaxGroupStreams, CRS_EINVAL, "stream count out of range");
+  const int want = std::min<int>(n, (int)e.groups.size()) - 1;
+  while ((int)e.side.size() < want) {
+    hipStream_t t = nullptr;
+    CRS_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+    e.side.push_back(t);
+    hipEvent_t ev = nullptr;
+    CRS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    e.join.push_back(ev);
+  }
+  if (!e.side.empty() && !e.fork) CRS_HIP(hipEventCreateWithFlags(&e.fork, hipEventDisableTiming));
+  e.nstreams = n;
+}
+
+void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const double* act) {
   const bool pinv = kind == OP_PI;
   const bool skip_done = act != nullptr;
-  const bool cap = capturing(s);
+  const bool cap = capturing(s0);
+  std::vector<int> run;
   for (int gi = 0; gi < (int)e.groups.size(); ++gi) {
-    ExecGroup& g = e.groups[gi];
+    const ExecGroup& g = e.groups[gi];
     // groups whose systems have all finished launch nothing (their partial
     // sums are read only for active systems): outside a capture from the
     // host's activity mirror, inside one from the live-group set it was
@@ -824,8 +844,31 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
     if (skip_done && !cap && active_maps(e, g, true) == 0) continue;
     if (skip_done && cap && !e.live[gi]) continue;
     // M_PI of merged observations: the bands merged into another band skip T^+
-    const bool pimask = pinv && g.pi_maps < g.nmaps;
     if (pinv && g.pi_maps == 0) continue;
+    run.push_back(gi);
+  }
+  // groups in order of work over the caller's stream and the side streams
+  // (each to the least loaded one)
+  const int nstr = std::min({e.nstreams, 1 + (int)e.side.size(), (int)run.size()});
+  std::vector<int64_t> load(nstr, 0);
+  std::vector<hipStream_t> gstream(e.groups.size(), s0);
+  if (nstr > 1) {
+    std::vector<int> order = run;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return e.groups[a].plan->fp64_triples * e.groups[a].nmaps > e.groups[b].plan->fp64_triples * e.groups[b].nmaps;
+    });
+    CRS_HIP(hipEventRecord(e.fork, s0));
+    for (int i = 1; i < nstr; ++i) CRS_HIP(hipStreamWaitEvent(e.side[i - 1], e.fork, 0));
+    for (int gi : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += (int64_t)(e.groups[gi].plan->fp64_triples * e.groups[gi].nmaps);
+      gstream[gi] = k == 0 ? s0 : e.side[k - 1];
+    }
+  }
+  for (int gi : run) {
+    ExecGroup& g = e.groups[gi];
+    hipStream_t s = gstream[gi];
+    const bool pimask = pinv && g.pi_maps < g.nmaps;
     const int tag = ((e.chunk_iter << 1) | (pinv ? 1 : 0)) * 1024 + gi;
     MapSkip skip;
     if (pimask) {
@@ -858,6 +901,10 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const dou
       launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
                          s);
     }
+  }
+  for (int i = 1; i < nstr; ++i) {
+    CRS_HIP(hipEventRecord(e.join[i - 1], e.side[i - 1]));
+    CRS_HIP(hipStreamWaitEvent(s0, e.join[i - 1], 0));
   }
 }
 
@@ -1314,7 +1361,7 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       uint64_t mask = 0;
       for (int gi = 0; gi < ng && gi < 64; ++gi)
         if (e.live[gi]) mask |= uint64_t(1) << gi;
-      const auto key = std::make_tuple(precond * 2 + (prof ? 1 : 0), first ? 1 : 0, k, mask);
+      const auto key = std::make_tuple((precond * 2 + (prof ? 1 : 0)) * 16 + e.nstreams, first ? 1 : 0, k, mask);
       auto itg = e.graphs.find(key);
       if (itg != e.graphs.end() && itg->second->rtol == rtol) return *itg->second;
       auto ge = std::make_unique<Exec::GraphEntry>();

@@ -169,6 +169,7 @@ struct MaskRunDel {
 };
 
 constexpr int kChunk = 8;         // PCG iterations per graph launch
+constexpr int kMaxGroupStreams = 8;  // streams the transform groups of an Exec may run on
 struct ExecStats {
   int iterations = 0;             // iterations of the slowest system
   int graph_launches = 0;
@@ -228,6 +229,16 @@ struct Exec {
   const int* vm_vidx = nullptr;                                // its device tables (in varmix)
   const double* vm_ybuf = nullptr;
   const int64_t* vm_yoff = nullptr;
+  // Transform groups are independent until the back-mix: exec_bands runs
+  // them on the caller's stream and on these side streams (default
+  // priority), forked from and joined back into the caller's stream by
+  // events (inside a graph capture the same calls become graph edges).
+  // nstreams: streams the groups run on (1: all on the caller's stream; set
+  // by exec_set_streams, part of a captured graph's key).
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  int nstreams = 1;
   ~Exec();
 };
 
@@ -256,6 +267,9 @@ void exec_diag(Exec& e, const double* r, double* z, hipStream_t s, const double*
 Work3 group_work(const Exec& e, int gi, int family, bool masked, bool pi = false);
 // the band half of exec_apply: every group's adjoint partial sums, no back-mix
 void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s, const double* act = nullptr);
+// Run the transform groups on up to n streams (1 <= n <= kMaxGroupStreams;
+// more than one group is needed for any concurrency); creates the streams.
+void exec_set_streams(Exec& e, int n);
 void exec_prior_inv(Exec& e, const double* x, double* y, hipStream_t s);
 // the band half of exec_rhs (data / omega_1 terms only)
 void exec_rhs_bands(Exec& e, const std::vector<std::vector<const double*>>& d,

@@ -70,6 +70,15 @@ struct TwCtx {
   }
 };
 
+// The ring's table exp(-i pi t / Nphi), t < 2 Nphi, read from global memory
+// (L2-resident: every ring of that length and every map shares it).  The
+// fold reads its phase factors here, so it need not wait for the LDS copy of
+// the tables.
+struct GlobalTw {
+  const double2* __restrict__ T;
+  __device__ __forceinline__ double2 at(int t) const { return T[t]; }
+};
+
 // cos(2 pi k / R) and sin(2 pi k / R), 1 <= k <= (R-1)/2, for the odd radices
 // (values correctly rounded from their closed forms).
 __device__ __forceinline__ constexpr double dft_cos(int R, int k) {
@@ -262,8 +271,9 @@ __device__ void dft_bluestein(double2* x, int n0, int M, const double2* __restri
 // Sum of g_m = (F^c_m - i F^s_m) e^{i m phi0} over m = m0, m0 + S, ... <= L,
 // e^{i m phi0} = conj(T[t_m]) with t_m = m num mod 2N stepping by tS; four
 // loads in flight per step, summed in order of m.
+template <class Tw>
 __device__ __forceinline__ double2 sum_g(const double2* __restrict__ ph, int m0, int S, int L, int t,
-                                         int tS, int twoN, const TwCtx& ring) {
+                                         int tS, int twoN, const Tw& ring) {
   double2 acc = make_double2(0.0, 0.0);
   int m = m0;
   auto add = [&](double2 F) {
@@ -284,8 +294,9 @@ __device__ __forceinline__ double2 sum_g(const double2* __restrict__ ph, int m0,
 
 // Folded spectrum c_k = (G_k + conj G_{-k}) / 2 with G_k the sum of g_m over
 // m = k mod N (0 <= k < N).
+template <class Tw>
 __device__ __forceinline__ double2 fold(const double2* __restrict__ ph, int k, int N, int L, int num,
-                                        const FastDiv& d2N, int stepN, const TwCtx& ring) {
+                                        const FastDiv& d2N, int stepN, const Tw& ring) {
   const double2 a = sum_g(ph, k, N, L, (int)d2N.mod((unsigned)k * (unsigned)num), stepN, 2 * N, ring);
   const int m1 = k == 0 ? 0 : N - k;
   const double2 b = sum_g(ph, m1, N, L, (int)d2N.mod((unsigned)m1 * (unsigned)num), stepN, 2 * N, ring);
@@ -330,8 +341,11 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
     for (int i = tid; i < 64; i += NT) wf2[i] = a.tw2[i];
     for (int u = tid; u < kBlueMax / 64; u += NT) wc2[u] = a.tw2[64 * u];
   }
-  __syncthreads();
+  // No barrier here: the LDS tables are first read after the barrier that
+  // follows the fold (synthesis) or the input load (adjoint), so the table
+  // copy and those global loads are in flight together.
   const TwCtx ring{wf, wc, 1};
+  const GlobalTw gring{Tg};
   // the FFT of length n0 (direct) or nf (Bluestein)
   const TwCtx fc = blue ? TwCtx{wf2, wc2, kBlueMax / nf} : TwCtx{wf, wc, twoN / n0};
   const double2* __restrict__ bf = blue ? a.bf + a.bfoff[r] : nullptr;
@@ -347,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
       double2* P = G + N;
       if (tid < S)
         P[tid] = sum_g(ph, tid, S, L, (int)d2N.mod((unsigned)tid * (unsigned)num),
-                       (int)d2N.mod((unsigned)S * (unsigned)num), twoN, ring);
+                       (int)d2N.mod((unsigned)S * (unsigned)num), twoN, gring);
       __syncthreads();
       for (int k = tid; k < N; k += NT) {
         double2 acc = P[k];
@@ -361,14 +375,14 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
         const double2 u = G[k], v = G[k == 0 ? 0 : N - k];
         return make_double2(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));
       }
-      return fold(ph, k, N, L, num, d2N, stepN, ring);
+      return fold(ph, k, N, L, num, d2N, stepN, gring);
     };
     for (int k = tid; k < n0; k += NT) {
       if (half) {
         const double2 ck = cfold(k);
         const double2 ch = cfold(k + n0);
         // Z_k = (c_k + c_{k+H}) + i e^{+2 pi i k / N} (c_k - c_{k+H})
-        const double2 e = conj2(ring.at(2 * k));
+        const double2 e = conj2(gring.at(2 * k));
         const double2 dd = cmul(e, csub(ck, ch));
         x[k] = make_double2(ck.x + ch.x - dd.y, ck.y + ch.y + dd.x);
       } else {

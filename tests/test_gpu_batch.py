@@ -75,6 +75,32 @@ def test_batch_matches_per_model_solves():
         print(f"problem {p}: {infog['iters'][p]} iterations", flush=True)
 
 
+def test_batch_group_streams_bitwise():
+    """Transform groups on four streams (graphs and the plain loop) give the
+    bitwise result of one stream: each group writes its own buffers and the
+    back-mix sums them in a fixed order after the join."""
+    torch, crsolve = _setup()
+    print("case batch group streams 1 vs 4, 6 problems, scale 8", flush=True)
+    probs, oms, models, data, _ = _batch_setup(6, 8, diag=True)
+    seeds = [1100 + i for i in range(len(models))]
+    batch = crsolve.Batch(models)
+    out = {}
+    for ns in (1, 4):
+        batch.set_streams(ns)
+        for g in (True, False):
+            x, info = batch.solve(d=data, seeds=seeds, mode="cr", precond="diag", rtol=1e-9,
+                                  maxiter=3000, use_graph=g)
+            assert info["status"] == 0
+            out[(ns, g)] = ([t.cpu().numpy() for t in x], list(info["iters"]))
+    for g in (True, False):
+        (x1, i1), (x4, i4) = out[(1, g)], out[(4, g)]
+        assert i1 == i4
+        for a, b in zip(x1, x4):
+            np.testing.assert_array_equal(a, b)
+    with pytest.raises(Exception):
+        batch.set_streams(9)
+
+
 def test_batch_problem_matches_oracle():
     """One problem of the batch against the oracle's CR solve with the same
     Philox draws (both driven to 1e-12)."""
