@@ -173,6 +173,7 @@ RingArgs ring_args(crs_grid g, int lmax) {
   r.phiden = g->d_phiden.p;
   r.nfac = g->d_nfac.p;
   r.fac = g->d_fac.p;
+  r.facm = g->d_facm.p;
   r.fftn = g->d_fftn.p;
   r.twoff = g->d_twoff.p;
   r.tw = g->d_tw.p;

@@ -95,6 +95,13 @@ std::vector<double2> bluestein_filter(int n, int M) {
   }
   host_fft_pow2(b);
   for (auto& v : b) v = make_double2(v.x / M, v.y / M);
+  // followed by the chirp w_d = exp(-i pi d^2 / n), d < n
+  for (int d = 0; d < n; ++d) {
+    double sv, cv;
+    const long long t = ((long long)d * d) % (2LL * n);
+    host_sincospi((double)t / n, &sv, &cv);
+    b.push_back(make_double2(cv, -sv));
+  }
   return b;
 }
 
@@ -168,6 +175,7 @@ void grid_finalize(crs_grid g, hipStream_t s) {
   // length whose largest prime factor exceeds 7 goes through Bluestein's
   // chirp convolution with a power-of-two FFT.
   std::vector<int> nfac(nr), fac((size_t)nr * kMaxFactors, 1), fftn(nr);
+  std::vector<unsigned> facm((size_t)nr * kMaxFactors, 0u);
   std::vector<int64_t> twoff(nr), bfoff(nr, -1);
   std::map<int, int64_t> tw_of, bf_of;
   std::vector<double2> tw, bf;
@@ -202,7 +210,14 @@ void grid_finalize(crs_grid g, hipStream_t s) {
     auto ff = factorize(nf);
     CRS_CHECK((int)ff.size() <= kMaxFactors, CRS_EUNSUPPORTED, "too many FFT factors");
     nfac[r] = (int)ff.size();
-    for (size_t i = 0; i < ff.size(); ++i) fac[(size_t)r * kMaxFactors + i] = ff[i];
+    {
+      unsigned ns = 1;
+      for (size_t i = 0; i < ff.size(); ++i) {
+        fac[(size_t)r * kMaxFactors + i] = ff[i];
+        facm[(size_t)r * kMaxFactors + i] = ns <= 1 ? 0u : (unsigned)(0xFFFFFFFFull / ns + 1);
+        ns *= (unsigned)ff[i];
+      }
+    }
     fftn[r] = nf;
     g->ring_maxn = std::max(g->ring_maxn, n);
     auto it = tw_of.find(n);
@@ -313,6 +328,7 @@ void grid_finalize(crs_grid g, hipStream_t s) {
   g->d_phiden.upload(g->phi0_den, s);
   g->d_nfac.upload(nfac, s);
   g->d_fac.upload(fac, s);
+  g->d_facm.upload(facm, s);
   g->d_twoff.upload(twoff, s);
   g->d_tw.upload(tw, s);
   g->d_zpair.upload(zp, s);

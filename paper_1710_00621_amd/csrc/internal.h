@@ -151,6 +151,7 @@ struct crs_grid_s {
   std::vector<int64_t> offset;
   // device ring tables
   crs::DevBuf<int> d_nphi, d_phinum, d_phiden, d_nfac, d_fac, d_fftn;
+  crs::DevBuf<unsigned> d_facm;
   crs::DevBuf<int64_t> d_offset, d_twoff, d_bfoff;
   crs::DevBuf<double2> d_bf;      // Bluestein filter spectra per distinct length
   crs::DevBuf<double2> d_tw2;     // exp(-2 pi i t / kBlueMax), t < kBlueMax
@@ -229,11 +230,12 @@ struct RingArgs {
   const int* phiden;
   const int* nfac;     // radices of the FFT length of each ring
   const int* fac;
+  const unsigned* facm;  // per stage: FastDiv multiplier of the stride Ns before it
   const int* fftn;     // FFT length: Nphi / 2 (even), Nphi (odd) or the Bluestein length
   const int64_t* twoff;
   const double2* tw;   // per distinct Nphi: exp(-i pi t / Nphi), t < 2 Nphi
   const int64_t* bfoff;
-  const double2* bf;
+  const double2* bf;    // per Bluestein length: filter spectrum [fftn], then the chirp [n0]
   const double2* tw2;
   int nring, lmax;
   int maxn, xcap;      // per launch class: longest ring, LDS data words

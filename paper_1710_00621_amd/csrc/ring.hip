@@ -52,6 +52,8 @@ struct FastDiv {
   unsigned d, m;
   __device__ __forceinline__ explicit FastDiv(unsigned dd)
       : d(dd), m(dd <= 1 ? 0u : (unsigned)(0xFFFFFFFFull / dd + 1)) {}
+  // with the multiplier precomputed on the host
+  __device__ __forceinline__ FastDiv(unsigned dd, unsigned mm) : d(dd), m(mm) {}
   __device__ __forceinline__ unsigned div(unsigned n) const { return d <= 1 ? n : __umulhi(n, m); }
   __device__ __forceinline__ unsigned mod(unsigned n) const { return n - div(n) * d; }
 };
@@ -171,11 +173,11 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], bool inv) {
 // + k + r Ns].  Every thread keeps its butterflies in registers across the
 // barrier, so the stage works in place.
 template <int R, int NT, int MAXN>
-__device__ void stage(double2* x, int n, int Ns, const TwCtx& C, bool inv) {
+__device__ void stage(double2* x, int n, int Ns, unsigned nsm, const TwCtx& C, bool inv) {
   constexpr int MAXIT = (MAXN / R + NT - 1) / NT;
   const int nb = n / R;
   const int span = nb / Ns;
-  const FastDiv dv((unsigned)Ns);
+  const FastDiv dv((unsigned)Ns, nsm);
   const int tid = threadIdx.x;
   double2 v[MAXIT][R];
 #pragma unroll
@@ -215,21 +217,22 @@ __device__ void stage(double2* x, int n, int Ns, const TwCtx& C, bool inv) {
 // In-place DFT of x[0..n) in LDS: forward exp(-2 pi i jk/n), inverse exp(+).
 // POW2: the length is a power of two (radix 8, 4 and 2 only).
 template <int NT, int MAXN, bool POW2>
-__device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, int nfac, const TwCtx& C,
-                        bool inv) {
+__device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, const unsigned* __restrict__ facm,
+                        int nfac, const TwCtx& C, bool inv) {
   int Ns = 1;
   for (int st = 0; st < nfac; ++st) {
     const int R = fac[st];
+    const unsigned m = facm[st];
     if (R == 8) {
-      stage<8, NT, MAXN>(x, n, Ns, C, inv);
+      stage<8, NT, MAXN>(x, n, Ns, m, C, inv);
     } else if (R == 4) {
-      stage<4, NT, MAXN>(x, n, Ns, C, inv);
+      stage<4, NT, MAXN>(x, n, Ns, m, C, inv);
     } else if (R == 2) {
-      stage<2, NT, MAXN>(x, n, Ns, C, inv);
+      stage<2, NT, MAXN>(x, n, Ns, m, C, inv);
     } else if constexpr (!POW2) {
-      if (R == 3) stage<3, NT, MAXN>(x, n, Ns, C, inv);
-      else if (R == 5) stage<5, NT, MAXN>(x, n, Ns, C, inv);
-      else if (R == 7) stage<7, NT, MAXN>(x, n, Ns, C, inv);
+      if (R == 3) stage<3, NT, MAXN>(x, n, Ns, m, C, inv);
+      else if (R == 5) stage<5, NT, MAXN>(x, n, Ns, m, C, inv);
+      else if (R == 7) stage<7, NT, MAXN>(x, n, Ns, m, C, inv);
     }
     Ns *= R;
   }
@@ -238,31 +241,29 @@ __device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, int nfac
 // DFT of length n0 through Bluestein's identity:
 //   X_k = w_k sum_n (x_n w_n) b_{k-n},  w_n = exp(-i pi n^2 / n0), b_d = conj(w_d),
 // a cyclic convolution of length M (x holds M words).  The inverse DFT is
-// conj(DFT(conj x)).  Chirp phases n^2 mod 2 n0 come from the ring table
-// (exp(-i pi t / Nphi), t < 2 Nphi) at t = (n^2 mod 2 n0) * cs.
+// conj(DFT(conj x)).  bf holds the filter spectrum (M words) followed by the
+// chirp w_n (n0 words), both precomputed on the host.
 template <int NT, int MAXN>
 __device__ void dft_bluestein(double2* x, int n0, int M, const double2* __restrict__ bf,
-                              const TwCtx& ring, int cs, const TwCtx& C, const int* __restrict__ fac,
+                              const TwCtx& C, const int* __restrict__ fac, const unsigned* __restrict__ facm,
                               int nfac, bool inv) {
   const int tid = threadIdx.x;
-  const unsigned twon = 2u * (unsigned)n0;
+  const double2* __restrict__ w = bf + M;
   for (int i = tid; i < M; i += NT) {
     double2 v = make_double2(0.0, 0.0);
     if (i < n0) {
       const double2 a = x[i];
-      const int t = (int)(((unsigned)i * (unsigned)i) % twon) * cs;
-      v = cmul(inv ? conj2(a) : a, ring.at(t));
+      v = cmul(inv ? conj2(a) : a, w[i]);
     }
     x[i] = v;
   }
   __syncthreads();
-  fft_lds<NT, MAXN, true>(x, M, fac, nfac, C, false);
+  fft_lds<NT, MAXN, true>(x, M, fac, facm, nfac, C, false);
   for (int i = tid; i < M; i += NT) x[i] = cmul(x[i], bf[i]);
   __syncthreads();
-  fft_lds<NT, MAXN, true>(x, M, fac, nfac, C, true);
+  fft_lds<NT, MAXN, true>(x, M, fac, facm, nfac, C, true);
   for (int i = tid; i < n0; i += NT) {
-    const int t = (int)(((unsigned)i * (unsigned)i) % twon) * cs;
-    const double2 v = cmul(x[i], ring.at(t));
+    const double2 v = cmul(x[i], w[i]);
     x[i] = inv ? conj2(v) : v;
   }
   __syncthreads();
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   const int num = a.phinum[r];
   const double2* __restrict__ Tg = a.tw + a.twoff[r];
   const int* __restrict__ fac = a.fac + (size_t)r * kMaxFactors;
+  const unsigned* __restrict__ facm = a.facm + (size_t)r * kMaxFactors;
   const int nfac = a.nfac[r];
   double2* __restrict__ ph = phase + (int64_t)map * pstride + (int64_t)r * (L + 1);
   const int twoN = 2 * N;
@@ -352,9 +354,20 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   const FastDiv d2N((unsigned)twoN), dN((unsigned)N);
   double* xd = reinterpret_cast<double*>(x);
 
+  // Wide even rings (N >= 2L, every HEALPix belt ring at L <= 2 Nside): each
+  // m <= L has its own bin (m = N / 2 = L shares the Nyquist bin with -m), so
+  // the fold and the unfold take one phase value per bin and the factors
+  // e^{-i pi t / N} straight from the ring's global table, t = m num < 2N
+  // (phi0 = pi num / N with num 0 or 1 on every grid built here).
+  const bool wide = half && 2 * L <= N;
+  auto gval = [&](int m) -> double2 {  // g_m = (F^c_m - i F^s_m) e^{i m phi0}
+    const double2 F = ph[m];
+    const double2 Fc = make_double2(F.x, -F.y);
+    return num ? cmulc(Fc, gring.at(m)) : Fc;
+  };
   if (mode == RING_SYNTH || mode == RING_ROUNDTRIP) {
     const int stepN = (int)d2N.mod((unsigned)N * (unsigned)num);
-    if (N <= NT) {
+    if (N <= NT && !wide) {
       // short ring: all threads fold.  Thread p < S (S = N floor(NT / N))
       // sums g_m over m = p mod S; G_k then adds the S / N partials of bin k.
       const int S = N * (NT / N);
@@ -378,7 +391,22 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
       return fold(ph, k, N, L, num, d2N, stepN, gring);
     };
     for (int k = tid; k < n0; k += NT) {
-      if (half) {
+      if (wide) {
+        // c_0 = Re g_0, c_k = g_k / 2 (0 < k < H), c_{k+H} = conj(g_{H-k}) / 2
+        // (0 < k), c_H = Re g_H (H <= L only when N = 2L)
+        double2 ck = k <= L ? gval(k) : make_double2(0.0, 0.0);
+        double2 ch = n0 - k <= L ? gval(n0 - k) : make_double2(0.0, 0.0);
+        if (k == 0) {
+          ck.y = 0.0;
+          ch.y = 0.0;
+        } else {
+          ck = make_double2(0.5 * ck.x, 0.5 * ck.y);
+          ch = make_double2(0.5 * ch.x, -0.5 * ch.y);
+        }
+        const double2 e = conj2(gring.at(2 * k));
+        const double2 dd = cmul(e, csub(ck, ch));
+        x[k] = make_double2(ck.x + ch.x - dd.y, ck.y + ch.y + dd.x);
+      } else if (half) {
         const double2 ck = cfold(k);
         const double2 ch = cfold(k + n0);
         // Z_k = (c_k + c_{k+H}) + i e^{+2 pi i k / N} (c_k - c_{k+H})
@@ -391,9 +419,9 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
     }
     __syncthreads();
     if (blue)
-      dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, true);
+      dft_bluestein<NT, MAXN>(x, n0, nf, bf, fc, fac, facm, nfac, true);
     else
-      fft_lds<NT, MAXN, !ODD>(x, n0, fac, nfac, fc, true);
+      fft_lds<NT, MAXN, !ODD>(x, n0, fac, facm, nfac, fc, true);
     if (mode == RING_SYNTH) {
       double* out = map_out + (int64_t)map * mstride + off;
       if (half) {
@@ -420,9 +448,9 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
     __syncthreads();
   }
   if (blue)
-    dft_bluestein<NT, MAXN>(x, n0, nf, bf, ring, N / n0, fc, fac, nfac, false);
+    dft_bluestein<NT, MAXN>(x, n0, nf, bf, fc, fac, facm, nfac, false);
   else
-    fft_lds<NT, MAXN, !ODD>(x, n0, fac, nfac, fc, false);
+    fft_lds<NT, MAXN, !ODD>(x, n0, fac, facm, nfac, fc, false);
 
   // forward DFT of the real ring data at bin k (0 <= k < N)
   auto spec = [&](int k) -> double2 {
@@ -449,6 +477,21 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
         const double2 X = cmul(spec(k), ring.at((int)d2N.mod(m2 * (unsigned)num)));
         ph[m] = make_double2(t0 + X.x, t0 - X.x);
       }
+    }
+    return;
+  }
+  if (wide) {
+    for (int m = tid; m <= L; m += NT) {
+      // F^_m from Z_m and Z_{H-m} (m = H only when N = 2L: bin 0's partner)
+      const int kk = m < n0 ? m : m - n0;
+      const int k2 = kk == 0 ? 0 : n0 - kk;
+      const double2 Zk = x[kk], Zc = conj2(x[k2]);
+      const double2 E = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+      const double2 D = csub(Zk, Zc);
+      const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);
+      double2 h = cadd(E, cmul(gring.at(2 * m), O));
+      if (num) h = cmul(h, gring.at(m));
+      ph[m] = make_double2(h.x, m == 0 ? 0.0 : -h.y);
     }
     return;
   }
