@@ -39,6 +39,8 @@ CASES = [
     (("gl", 7, 2046), 1100, 1),  # even length 2 * 3 * 11 * 31: half-length Bluestein
     (("gl", 5, 4375), 40, 1),    # odd 5^4 * 7 above 4096: full-length direct FFT, longest tier
     (("gl", 3, 8190), 30, 2),    # 8190 = 2 * 4095 (factor 13): Bluestein of 8192 points
+    (("healpix", 37), 90, 5),    # Bluestein caps, five maps
+    (("gl", 6, 7), 9, 4),        # odd aliasing rings, four maps
 ]
 
 
