@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(name, nprob, crsolve, inputs, torch, dev):
+def build_workload(name, nprob, crsolve, inputs, torch, dev, with_mask=True):
     grids = {}
 
     def grid(spec):
@@ -62,7 +62,7 @@ def build_workload(name, nprob, crsolve, inputs, torch, dev):
         gl = [grid(b["grid"]) for b in prob["bands"]]
         taus = inputs.inverse_noise_maps(prob, lambda spec: grid(spec).pixel_centres())
         model = crsolve.model_from_problem(prob, taus, gl, diag=True)
-        if prob["mask"] is not None:
+        if with_mask and prob["mask"] is not None:
             # the mask-restricted preconditioner of M_add (setup, outside the timed region)
             mgrid, mk = crsolve.mask_of_problem(prob, taus, gl)
             model.set_mask(mgrid, mk)
@@ -381,7 +381,9 @@ def main():
         return
     t0 = time.time()
     free0 = torch.cuda.mem_get_info(dev)[0]
-    probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev)
+    # the mask hierarchies (M_add) only where a solve uses them
+    need_mask = a.precond == "add" or a.workload == "masked" or (a.workload == "batched" and not a.no_plain)
+    probs, grids = build_workload(a.workload, a.nprob, crsolve, inputs, torch, dev, with_mask=need_mask)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log(f"setup {setup_s:.1f}s for {len(probs)} problems")
