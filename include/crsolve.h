@@ -32,7 +32,9 @@
  * Allocation: create calls allocate; apply/solve calls allocate nothing
  *   once a handle has seen the largest nrhs it is used with (workspaces grow
  *   on the first call with a larger nrhs).  sht_synth / sht_adjoint allocate
- *   per-(grid, lmax) tables on their first call for that pair.
+ *   per-(grid, lmax) tables on their first call for that pair and grow the
+ *   grid's transform workspace on a call with more maps; crs_sht_reserve
+ *   does both up front.
  */
 #ifndef CRSOLVE_H
 #define CRSOLVE_H
@@ -103,6 +105,15 @@ int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_st
               double* map, int64_t map_stride, crs_stream s);
 int sht_adjoint(crs_grid g, int lmax, int nmaps, const double* map, int64_t map_stride,
                 double* alm, int64_t alm_stride, crs_stream s);
+
+/* crs_sht_reserve: setup for the transforms of Sect. 2.1 on (g, lmax) with
+ * up to nmaps maps: builds the (grid, lmax) Legendre tables and grows the
+ * grid's transform workspace (hat vectors, phase array, per-tile partial sums
+ * sized for any kernel variant), so that later sht_synth / sht_adjoint calls
+ * on this grid with lmax and at most nmaps maps allocate nothing.
+ * Synchronises the stream.  Errors: CRS_EINVAL (NULL grid, lmax < 0,
+ * nmaps < 1), CRS_ENOMEM. */
+int crs_sht_reserve(crs_grid g, int lmax, int nmaps, crs_stream s);
 
 /* sht_adjoint_noalloc: sht_adjoint for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

@@ -61,6 +61,7 @@ _SIGS = {
     "crs_grid_pixel_centres": (ctypes.c_int, [vp, c_double_p, c_double_p]),
     "crs_grid_weights": (ctypes.c_int, [vp, c_double_p]),
     "crs_grid_destroy": (ctypes.c_int, [vp]),
+    "crs_sht_reserve": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp]),
     "sht_synth": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp,
                                  ctypes.c_int64, vp]),
     "sht_adjoint": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp,

@@ -83,6 +83,11 @@ class Grid:
                                            phi.ctypes.data_as(c_double_p)))
         return z, phi
 
+    def reserve(self, lmax, nmaps, device=None):
+        """Build the (grid, lmax) tables and the transform workspace for up to
+        nmaps maps, so later sht_synth / sht_adjoint calls allocate nothing."""
+        check(lib().crs_sht_reserve(self._h, int(lmax), int(nmaps), _stream(device)))
+
     def weights(self):
         w = np.empty(self.npix)
         check(lib().crs_grid_weights(self._h, w.ctypes.data_as(c_double_p)))

@@ -294,6 +294,25 @@ int crs_kernel_stats_reset(void) {
   return CRS_OK;
 }
 
+int crs_sht_reserve(crs_grid g, int lmax, int nmaps, crs_stream st) {
+  return guarded([&] {
+    CRS_CHECK(g != nullptr, CRS_EINVAL, "grid is NULL");
+    CRS_CHECK(lmax >= 0 && nmaps >= 1, CRS_EINVAL, "lmax < 0 or nmaps < 1");
+    hipStream_t s = (hipStream_t)st;
+    ShtPlan& p = get_plan(g, lmax, s);
+    if (!g->work) g->work = std::make_unique<GridWork>();
+    GridWork& w = *g->work;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 1);
+    const int64_t pst = (int64_t)g->nring * (lmax + 1);
+    w.uhat.alloc((size_t)nmaps * nalm);
+    w.phase.alloc((size_t)nmaps * pst);
+    // the largest tile count of any adjoint variant (one 64-pair tile per wave)
+    w.vpart.alloc((size_t)((p.npairs + 63) / 64) * nmaps * nalm);
+    CRS_HIP(hipStreamSynchronize(s));
+    return CRS_OK;
+  });
+}
+
 int sht_synth(crs_grid g, int lmax, int nmaps, const double* alm, int64_t alm_stride, double* map,
               int64_t map_stride, crs_stream st) {
   return guarded([&] {

@@ -341,3 +341,32 @@ def test_sht_nside2048_l6000_sampled():
     lhs = float((yx * y).sum())
     rhs = float((x * got_a).sum())
     assert abs(lhs - rhs) / float(yx.norm() * y.norm()) < 1e-13
+
+
+def test_reserve_then_transforms_allocate_nothing():
+    """crs_sht_reserve builds the tables and the workspace up front: the
+    transforms that follow (up to the reserved map count) leave the device's
+    free memory unchanged and match the transforms of another grid object."""
+    torch, crsolve = _setup()
+    print("case reserve: healpix 64, lmax 128, 5 maps", flush=True)
+    lmax, nm = 128, 5
+    gen = torch.Generator(device="cpu").manual_seed(41)
+    g2 = crsolve.Grid.healpix(64)
+    alm = torch.randn(nm, (lmax + 1) ** 2, generator=gen, dtype=torch.float64).cuda()
+    maps = torch.randn(nm, g2.npix, generator=gen, dtype=torch.float64).cuda()
+    out_map = torch.empty(nm, g2.npix, dtype=torch.float64, device="cuda")
+    out_alm = torch.empty(nm, (lmax + 1) ** 2, dtype=torch.float64, device="cuda")
+    # reference on a grid of its own (also warms torch's allocator for these shapes)
+    ref_map = crsolve.sht_synth(g2, lmax, alm[:2]).cpu().numpy()
+    ref_alm = crsolve.sht_adjoint(g2, lmax, maps[:2]).cpu().numpy()
+    g = crsolve.Grid.healpix(64)
+    g.reserve(lmax, nm)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for k in (nm, 2):
+        crsolve.sht_synth(g, lmax, alm[:k], out=out_map[:k])
+        crsolve.sht_adjoint(g, lmax, maps[:k], out=out_alm[:k])
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    assert _rel(out_map[:2].cpu().numpy(), ref_map) < 1e-13
+    assert _rel(out_alm[:2].cpu().numpy(), ref_alm) < 1e-13
