@@ -97,6 +97,7 @@ struct DevBuf {
 constexpr int kMaxRing = 8192;   // pixels per ring (the FFT stays LDS resident)
 constexpr int kMaxFactors = 16;  // radices per ring length
 constexpr int kBlueMax = 8192;   // longest Bluestein convolution (power of two)
+constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes one workgroup may use (gfx950)
 
 // ---------------------------------------------------------------- grids
 // Per-(grid, lmax) Legendre plan: start table and recurrence tables.

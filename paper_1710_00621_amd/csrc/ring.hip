@@ -526,6 +526,7 @@ void launch_ring(crs_grid g, int lmax, RingMode mode, int nmaps, double2* phase,
                          (rc.blue ? 64 + kBlueMax / 64 : 0) + rc.gcap;
     a.any_blue = rc.blue ? 1 : 0;
     const size_t lds = words * sizeof(double2);
+    CRS_CHECK(lds <= kMaxLds, CRS_EUNSUPPORTED, "ring class needs " + std::to_string(lds) + " bytes of LDS");
     switch (rc.tier * 2 + (rc.odd ? 1 : 0)) {
 #define CRS_RING(T, NT, MAXN, ODD)                                                                   \
   case T * 2 + ODD:                                                                                  \
