@@ -247,7 +247,8 @@ int crs_model_merge_observations(crs_model m, const int* group, crs_stream s);
  * share one band-limit (else CRS_EUNSUPPORTED).  The preconditioner
  * CRS_PRECOND_ADD is M_add = M_PI + M_mask (Sect. 4.2).
  * crs_model_set_mask: grid: HEALPix; mask: host, npix bytes, nonzero =
- * masked; opts: NULL or fields 0 for the defaults (0.05, 0.2, 1000, 1e-6).
+ * masked; opts: NULL or fields 0 for the defaults (0.05, 0.2, 1000, 1e-6,
+ * J taken as I).
  * The grid must outlive the model.  Setup: allocates, builds the level grids
  * and tables, eigendecomposes the bottom level on the device (rocSOLVER),
  * synchronises the stream.
@@ -259,6 +260,9 @@ typedef struct {
   double omega;
   int nbottom;
   double rcond;
+  int exact_j;  /* nonzero: apply J = Y_h^T W_h Y_h (masked pixels) exactly in
+                   the cycle, four more transforms per level; the cycle is then
+                   the textbook V-cycle, symmetric (J taken as I otherwise) */
 } crs_mask_opts;
 int crs_model_set_mask(crs_model m, crs_grid grid, const uint8_t* mask, const crs_mask_opts* opts,
                        crs_stream s);

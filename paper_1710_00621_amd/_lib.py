@@ -42,7 +42,7 @@ class BandDesc(ctypes.Structure):
 
 class MaskOpts(ctypes.Structure):
     _fields_ = [("lowpass_r2", ctypes.c_double), ("omega", ctypes.c_double),
-                ("nbottom", ctypes.c_int), ("rcond", ctypes.c_double)]
+                ("nbottom", ctypes.c_int), ("rcond", ctypes.c_double), ("exact_j", ctypes.c_int)]
 
 
 class ModelDesc(ctypes.Structure):

@@ -248,14 +248,15 @@ class Model:
         arr = (ctypes.c_int * self.nbands)(*g)
         check(lib().crs_model_merge_observations(self._h, arr, _stream()))
 
-    def set_mask(self, grid, mask, lowpass_r2=0.0, omega=0.0, nbottom=0, rcond=0.0):
+    def set_mask(self, grid, mask, lowpass_r2=0.0, omega=0.0, nbottom=0, rcond=0.0, exact_j=False):
         """Build the mask-restricted preconditioner (M_mask; CRS_PRECOND_ADD =
         M_PI + M_mask) on a HEALPix grid; mask: bool / uint8 per pixel (True =
-        masked).  Zero option values select the defaults."""
+        masked).  Zero option values select the defaults; exact_j applies
+        J = Y^T W Y exactly in the cycle (symmetric V-cycle)."""
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if m.shape != (grid.npix,):
             raise ValueError("mask must have one entry per pixel of the grid")
-        opts = _lib.MaskOpts(float(lowpass_r2), float(omega), int(nbottom), float(rcond))
+        opts = _lib.MaskOpts(float(lowpass_r2), float(omega), int(nbottom), float(rcond), 1 if exact_j else 0)
         check(lib().crs_model_set_mask(self._h, grid._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                        ctypes.byref(opts), _stream()))
         self.mask_grid = grid

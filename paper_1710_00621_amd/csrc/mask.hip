@@ -129,6 +129,8 @@ struct MaskMG {
   int L0 = 0;
   double omega = 0.2, rcond = 1e-6, r2half = 0.05;
   int nbottom = 1000;
+  bool exact_j = false;          // J = Y_h^T W_h Y_h applied exactly (else taken as I)
+  DevBuf<double> ones;           // l-table of ones (unscaled subtraction in k_from_parts)
   DevBuf<double> rtop;           // r_l at L0 (the low-pass of Z)
   DevBuf<double> gplus;          // [ncm][n_b][n_b] bottom pseudo-inverses
   ~MaskMG() {
@@ -149,6 +151,7 @@ struct MaskRunImpl {
   DevBuf<int> mc, mapsys;                    // per map: masked component index, system
   DevBuf<int64_t> off_top;                   // per map: offset of its component vector in the stacked vectors
   std::vector<DevBuf<double>> b, x, y, u, rt, ct;  // per level
+  std::vector<DevBuf<double>> jv;            // per level (exact J): J applied to a vector at L_h
   std::vector<DevBuf<double>> sm;            // per level: per-map smoother constant
   ShtScratch sc;                              // transform scratch of every level
 };
@@ -172,6 +175,19 @@ int adjoint_ws(crs_grid g, int L, int nm, const double* map, MaskRun& r, MapSkip
 void map_op(int op, MaskRun& r, double* x, const double* b, const double* y, const double* ind, const double* sm,
             double alpha, int64_t npix, MapSkip skip, hipStream_t s) {
   launch_map_op(op, x, b, y, ind, sm, alpha, npix, r.nm, skip, s);
+}
+
+// out = J v = W_h Y_h^T (mask_h) Y_h v at band-limit L, v given as hat
+// vectors in the scratch; map: a level map buffer for the synthesis
+void apply_j(const MaskLevel& lv, int L, const ShtPlan& p, MaskRun& r, double* map, double* out, MapSkip skip,
+             hipStream_t s) {
+  const int nm = r.nm;
+  synth_ws(lv.grid, L, nm, r.sc.hat.p, map, r, skip, s);
+  map_op(MOP_MASK, r, map, nullptr, nullptr, lv.ind.p, nullptr, 0.0, lv.grid->npix, skip, s);
+  const int nt = adjoint_ws(lv.grid, L, nm, map, r, skip, s);
+  launch_from_parts(out, (const int64_t*)nullptr, L, 0, lv.w, p.hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(L),
+                    (const double*)nullptr, 0, (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0,
+                    r.mc.p, nm, skip, s);
 }
 
 void vcycle(const MaskMG& mg, MaskRun& r, int h, MapSkip skip, hipStream_t s) {
@@ -199,9 +215,19 @@ void vcycle(const MaskMG& mg, MaskRun& r, int h, MapSkip skip, hipStream_t s) {
   launch_from_parts(r.u[h].p, (const int64_t*)nullptr, Lh, 0, 1.0,
                      ph.hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(Lh), (const double*)nullptr, 0,
                      (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, nm, skip, s);
-  // r~ = W_h Y_h^T b - D_h u, at L_H                        (L_H, N_h)
+  // exact J: jv = J D_h u = W_h Y_h^T (mask_h) Y_h D_h u       (L_h, N_h)
+  if (mg.exact_j) {
+    launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p, Lh, (const int64_t*)nullptr, nalm_of(Lh),
+                    (const double*)nullptr, 0, (int64_t)0, lv.D.p, Lh + 1, r.mc.p, nm, skip, s);
+    apply_j(lv, Lh, ph, r, r.y[h].p, r.jv[h].p, skip, s);
+  }
+  // r~ = W_h Y_h^T b - D_h u (J D_h u with exact J), at L_H  (L_H, N_h)
   nt = adjoint_ws(lv.grid, LH, nm, r.b[h].p, r, skip, s);
-  {
+  if (mg.exact_j) {
+    launch_from_parts(r.rt[h].p, (const int64_t*)nullptr, LH, 0, lv.w, pH.hs.p, r.sc.parts.p, nt,
+                      (int64_t)nm * nalm_of(LH), (const double*)nullptr, 0, r.jv[h].p, Lh, nalm_of(Lh),
+                      mg.ones.p, 0, r.mc.p, nm, skip, s);
+  } else {
     launch_from_parts(r.rt[h].p, (const int64_t*)nullptr, LH, 0,
                        lv.w, pH.hs.p, r.sc.parts.p, nt, (int64_t)nm * nalm_of(LH), (const double*)nullptr, 0, r.u[h].p, Lh,
                        nalm_of(Lh), lv.D.p, Lh + 1, r.mc.p, nm, skip, s);
@@ -227,9 +253,18 @@ void vcycle(const MaskMG& mg, MaskRun& r, int h, MapSkip skip, hipStream_t s) {
   synth_ws(lv.grid, LH, nm, r.sc.hat.p, r.y[h].p, r, skip, s);
   map_op(MOP_AXPY_MASK, r, r.x[h].p, nullptr, r.y[h].p, lv.ind.p, nullptr, lv.w, np, skip, s);
   // x += M_h (b - (mask_h) Y_h D_h (u + c~))                 (L_h, N_h)
-  launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p,
-                     Lh, (const int64_t*)nullptr, nalm_of(Lh), (const double*)r.ct[h].p, LH, nalm_of(LH), lv.D.p,
-                     Lh + 1, r.mc.p, nm, skip, s);
+  // (exact J: u + J c~, J c~ = W_h Y_h^T (mask_h) Y_h c~ at L_h)
+  if (mg.exact_j) {
+    launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.ct[h].p, LH, (const int64_t*)nullptr, nalm_of(LH),
+                    (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, 0, r.mc.p, nm, skip, s);
+    apply_j(lv, Lh, ph, r, r.y[h].p, r.jv[h].p, skip, s);
+    launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p, Lh, (const int64_t*)nullptr, nalm_of(Lh),
+                    (const double*)r.jv[h].p, Lh, nalm_of(Lh), lv.D.p, Lh + 1, r.mc.p, nm, skip, s);
+  } else {
+    launch_hat_from(r.sc.hat.p, Lh, ph.hs.p, (const double*)r.u[h].p,
+                       Lh, (const int64_t*)nullptr, nalm_of(Lh), (const double*)r.ct[h].p, LH, nalm_of(LH), lv.D.p,
+                       Lh + 1, r.mc.p, nm, skip, s);
+  }
   CRS_HIP(hipGetLastError());
   synth_ws(lv.grid, Lh, nm, r.sc.hat.p, r.y[h].p, r, skip, s);
   map_op(MOP_POST, r, r.x[h].p, r.b[h].p, r.y[h].p, lv.ind.p, r.sm[h].p, 0.0, np, skip, s);
@@ -246,6 +281,7 @@ void build_mask(crs_model m, crs_grid g, const uint8_t* mask, const crs_mask_opt
     if (o->omega > 0) mg->omega = o->omega;
     if (o->nbottom > 0) mg->nbottom = o->nbottom;
     if (o->rcond > 0) mg->rcond = o->rcond;
+    mg->exact_j = o->exact_j != 0;
   }
   CRS_CHECK(mg->r2half < 1.0, CRS_EINVAL, "lowpass_r2 must be in (0, 1)");
   for (int k = 0; k < m->ncomp; ++k) {
@@ -304,6 +340,8 @@ void build_mask(crs_model m, crs_grid g, const uint8_t* mask, const crs_mask_opt
   std::vector<double> rl(L0 + 1);
   for (int l = 0; l <= L0; ++l) rl[l] = std::exp(-beta * (double)l * l * (l + 1.0) * (l + 1.0));
   mg->rtop.upload(rl, s);
+  const std::vector<double> ones_h((size_t)L0 + 1, 1.0);  // alive until the stream sync below
+  mg->ones.upload(ones_h, s);
   std::vector<std::vector<double>> d(ncm, std::vector<double>(L0 + 1, 0.0));
   for (int c = 0; c < ncm; ++c)
     for (int l = 0; l <= L0; ++l) d[c][l] = rl[l] * rl[l] * m->invcl[mg->comps[c]][l];
@@ -445,6 +483,7 @@ MaskRun& mask_run(Exec& e, int p, hipStream_t s) {
   r->rt.resize(nl);
   r->ct.resize(nl);
   r->sm.resize(nl);
+  r->jv.resize(nl);
   for (int h = 0; h < nl; ++h) {
     const MaskLevel& lv = mg.levels[h];
     const size_t np = (size_t)lv.grid->npix * r->nm;
@@ -457,6 +496,7 @@ MaskRun& mask_run(Exec& e, int p, hipStream_t s) {
     std::vector<int> Ls = {lv.lmax};
     if (h + 1 < nl) Ls.push_back(mg.levels[h + 1].lmax);
     r->u[h].alloc((size_t)nalm_of(lv.lmax) * r->nm);
+    if (mg.exact_j && h + 1 < nl) r->jv[h].alloc((size_t)nalm_of(lv.lmax) * r->nm);
     if (h + 1 < nl) {
       r->rt[h].alloc((size_t)nalm_of(Ls[1]) * r->nm);
       r->ct[h].alloc((size_t)nalm_of(Ls[1]) * r->nm);

@@ -92,6 +92,32 @@ def test_pcg_add_matches_oracle(name, scale, index):
     assert abs(info["iters"][0] - ref.iters) <= 2
 
 
+@pytest.mark.parametrize("name,scale,index", [("batched", 4, 5), ("masked", 16, 0)])
+def test_apply_mask_exact_j_matches_oracle(name, scale, index):
+    """The cycle with J = Y^T W Y applied exactly (crs_mask_opts.exact_j)
+    against the oracle's cycle with exact J, element by element, and that
+    cycle's symmetry <M a, b> = <a, M b>."""
+    torch, crsolve = _setup()
+    print(f"case apply_mask exact J {name} scale {scale} index {index}", flush=True)
+    prob, om, _, _, taus, grids = _case(name, scale, index)
+    gl = [grids[b["grid"]] for b in prob["bands"]]
+    gm = crsolve.model_from_problem(prob, taus, gl, diag=False)
+    mgrid, m = crsolve.mask_of_problem(prob, taus, gl)
+    gm.set_mask(mgrid, m, exact_j=True)
+    Mj = mask.MaskPrecond(om, mgrid.spec[1], m, exact_j=True)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((2, om.n))
+    got = gm.apply_mask(torch.tensor(x, device="cuda")).cpu().numpy()
+    for i in range(2):
+        ref = Mj(x[i])
+        err = rel_max(got[i], ref)
+        print(f"  rhs {i}: max-abs rel error {err:.2e}", flush=True)
+        assert err < 1e-9
+    sym = abs(got[0] @ x[1] - x[0] @ got[1]) / (abs(got[0] @ x[1]) + 1e-300)
+    print(f"  symmetry defect {sym:.2e}", flush=True)
+    assert sym < 1e-10
+
+
 def test_batch_add_matches_per_model_solves():
     """M_add through a batch of small problems (graphs and no graphs) equals
     each model's own M_add solve."""
