@@ -532,6 +532,31 @@ __global__ void k_pi_flags(double* __restrict__ flag, const int* __restrict__ ke
   flag[kActStride * j] = on ? 1.0 : 0.0;
 }
 
+// The maps of a group that a launch processes (not skipped), ascending, and
+// their count: the Legendre kernels then run dense groups of active maps
+// (one block; a thread takes a contiguous run of maps).
+__global__ __launch_bounds__(256) void k_compact(MapSkip skip, int nmaps, int* __restrict__ mlist,
+                                                 int* __restrict__ mcount) {
+  __shared__ int cnt[256];
+  const int t = threadIdx.x;
+  const int per = (nmaps + 255) / 256;
+  const int b0 = min(nmaps, t * per), b1 = min(nmaps, b0 + per);
+  int c = 0;
+  for (int j = b0; j < b1; ++j) c += skip.off(j) ? 0 : 1;
+  cnt[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive prefix sum
+    const int v = t >= o ? cnt[t - o] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int pos = cnt[t] - c;
+  for (int j = b0; j < b1; ++j)
+    if (!skip.off(j)) mlist[pos++] = j;
+  if (t == 255) mcount[0] = cnt[255];
+}
+
 inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
 
 void mix_back(Exec& e, double* out, const double* din, int dmode, int dsqrt, int usep, hipStream_t s,
@@ -652,6 +677,8 @@ std::unique_ptr<Exec> make_exec(const std::vector<crs_model>& models, int nrhs, 
     g.nalm = (int64_t)(g.lmax + 1) * (g.lmax + 1);
     g.pst = (int64_t)g.grid->nring * (g.lmax + 1);
     g.uhat.alloc((size_t)g.nmaps * g.nalm);
+    g.mlist.alloc((size_t)g.nmaps);
+    g.mcount.alloc(1);
     g.phase.alloc((size_t)g.nmaps * g.pst);
     g.leg = autotune ? leg_autotune(leg_args(g.grid, *g.plan), g.nmaps, g.uhat.p, g.phase.p, s)
                      : leg_choice(g.plan->npairs, g.lmax, g.nmaps);
@@ -887,6 +914,15 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const do
     CRS_HIP(hipGetLastError());
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
+    if (skip.act) {
+      // the Legendre launches take the active maps compacted (a launch late
+      // in a solve then runs few dense groups instead of many sparse ones)
+      hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, skip, g.nmaps, g.mlist.p, g.mcount.p);
+      CRS_HIP(hipGetLastError());
+      la.mlist = g.mlist.p;
+      la.mcount = g.mcount.p;
+      la.skip = MapSkip{};
+    }
     {
       ProfScope ps(FAM_LEG_SYNTH, group_work(e, gi, FAM_LEG_SYNTH, skip_done, pinv), s, tag);
       launch_leg_synth(g.leg, la, g.nmaps, g.uhat.p, g.nalm, g.phase.p, g.pst, s);

@@ -194,6 +194,11 @@ struct LegArgs {
   const double* zpair;    // [npairs]
   int lmax, npairs, nring;
   MapSkip skip;
+  // optional compaction: the launch's map slots s < *mcount are the maps
+  // mlist[s] (ascending), the slots past *mcount are empty; without it slot
+  // s is map s.  Both device pointers, set together.
+  const int* mlist = nullptr;
+  const int* mcount = nullptr;
 };
 // Which Legendre kernels run for a (ring pairs, L, maps) shape: synthesis on
 // the matrix cores or vector FP64 with syn_r ring pairs per lane; adjoint on

@@ -245,6 +245,19 @@ __device__ __forceinline__ void syn_step(SynAcc<NM, R>& A, Grp<R>& G, const LegA
   syn_swap<NM, R>(A);
 }
 
+// map slots of a launch (see LegArgs::mlist)
+__device__ __forceinline__ int leg_nslots(const LegArgs& a, int nmaps) {
+  return a.mcount ? __builtin_amdgcn_readfirstlane(*a.mcount) : nmaps;
+}
+__device__ __forceinline__ int leg_map(const LegArgs& a, int slot) { return a.mlist ? a.mlist[slot] : slot; }
+// some slot of [s0, s0 + n) holds a map to process
+__device__ __forceinline__ bool leg_any(const LegArgs& a, int s0, int n, int ns) {
+  if (!a.skip.act) return s0 < ns;
+  bool any = false;
+  for (int k = 0; k < n && s0 + k < ns; ++k) any = any || !a.skip.off(leg_map(a, s0 + k));
+  return any;
+}
+
 template <int NM, int R, bool HAS_S>
 __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, int lane, int nmaps, int map0,
                                            const double* __restrict__ uhat, int64_t ustride,
@@ -255,7 +268,7 @@ __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, in
   cdouble* ub[NM];
 #pragma unroll
   for (int k = 0; k < NM; ++k)
-    ub[k] = as_const(uhat + (int64_t)min(map0 + k, nmaps - 1) * ustride + moff(L, m) - m);
+    ub[k] = as_const(uhat + (int64_t)leg_map(a, min(map0 + k, nmaps - 1)) * ustride + moff(L, m) - m);
   Grp<R> G;
   grp_init<R>(G, a, m, base, lane);
   SynAcc<NM, R> A;
@@ -292,7 +305,7 @@ __device__ __forceinline__ void synth_wave(const LegArgs& a, int m, int base, in
       const double oc = x_is_odd ? A.X[j][k][0] : A.Y[j][k][0];
       const double os = x_is_odd ? A.X[j][k][1] : A.Y[j][k][1];
       if (p < a.npairs && map0 + k < nmaps) {
-        double2* ph = phase + (int64_t)(map0 + k) * pstride;
+        double2* ph = phase + (int64_t)leg_map(a, map0 + k) * pstride;
         ph[(int64_t)p * (L + 1) + m] = make_double2(ec + oc, es + os);
         if (rs != p) ph[(int64_t)rs * (L + 1) + m] = make_double2(ec - oc, es - os);
       }
@@ -323,15 +336,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(LegArgs a, int nmaps, const d
   const int lane = threadIdx.x & 63;
   const int base = tile * 64 * R;
   const int map0 = blockIdx.y * NM;
-  if (a.skip.act) {
-    bool any = false;
-    for (int k = 0; k < NM && map0 + k < nmaps; ++k) any = any || !a.skip.off(map0 + k);
-    if (!any) return;
-  }
+  const int ns = leg_nslots(a, nmaps);
+  if (!leg_any(a, map0, NM, ns)) return;
   if (m == 0)
-    synth_wave<NM, R, false>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
+    synth_wave<NM, R, false>(a, m, base, lane, ns, map0, uhat, ustride, phase, pstride);
   else
-    synth_wave<NM, R, true>(a, m, base, lane, nmaps, map0, uhat, ustride, phase, pstride);
+    synth_wave<NM, R, true>(a, m, base, lane, ns, map0, uhat, ustride, phase, pstride);
 }
 
 // ------------------------------------------------------ synthesis, MFMA
@@ -366,11 +376,8 @@ __global__ __launch_bounds__(256) void k_leg_synth_mfma(LegArgs a, int nmaps, co
   const int L = a.lmax;
   if (m > L) return;
   const int mg = blockIdx.y;
-  if (a.skip.act) {
-    bool any = false;
-    for (int k = 0; k < 8 && mg * 8 + k < nmaps; ++k) any = any || !a.skip.off(mg * 8 + k);
-    if (!any) return;
-  }
+  const int ns = leg_nslots(a, nmaps);
+  if (!leg_any(a, mg * 8, 8, ns)) return;
   double* lam = lamsh[wave];
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, kq = lane >> 4;
@@ -381,10 +388,11 @@ __global__ __launch_bounds__(256) void k_leg_synth_mfma(LegArgs a, int nmaps, co
   const double2 st = valid ? a.ms[(size_t)m * a.npairs + p] : make_double2(0.0, 0.0);
   // B column of this lane: map mg * 8 + j / 2, part j & 1 (cos, sin)
   const int j = i16;
-  const int map = mg * 8 + (j >> 1), cs = j & 1;
+  const int slot = mg * 8 + (j >> 1), cs = j & 1;
+  const bool sok = slot < ns;
+  const int map = sok ? leg_map(a, slot) : 0;
   const double* __restrict__ ub =
-      (map < nmaps && !(m == 0 && cs == 1)) ? uhat + (int64_t)map * ustride + moff(L, m) + cs * (L - m + 1) - m
-                                           : nullptr;
+      (sok && !(m == 0 && cs == 1)) ? uhat + (int64_t)map * ustride + moff(L, m) + cs * (L - m + 1) - m : nullptr;
   cdouble* gb = as_const(a.g + tri(L, m) - m);  // 8 zeros follow the table
   // B loads are unconditional (clamped index, then masked) so that the
   // in-order vector-memory counter lets the next block's loads stay in flight
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(256) void k_leg_synth_mfma(LegArgs a, int nmaps, co
     }
   }
   // D[rb][row = kq + 4 r][col = j]: ring pair tile*64 + 16 rb + kq + 4 r
-  if (map >= nmaps) return;
+  if (!sok) return;
   double* ph = reinterpret_cast<double*>(phase + (int64_t)map * pstride);
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
@@ -547,7 +555,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
     const int rs = a.nring - 1 - pc;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-      const double2* ph = phase + (int64_t)min(map0 + k, nmaps - 1) * pstride;
+      const double2* ph = phase + (int64_t)leg_map(a, min(map0 + k, nmaps - 1)) * pstride;
       const double2 hn = valid ? ph[(int64_t)pc * (L + 1) + m] : make_double2(0.0, 0.0);
       const double2 hs = (valid && rs != pc) ? ph[(int64_t)rs * (L + 1) + m] : make_double2(0.0, 0.0);
       if (valid && rs == pc) {
@@ -573,7 +581,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
     const int nl = l0 - m;
     const int ll = i % nl, rest = i / nl, cs = rest & 1, k = rest >> 1;
     if ((cs == 1 && !HAS_S) || map0 + k >= nmaps) continue;
-    vbase[(int64_t)(map0 + k) * vstride + cs * nsl + ll] = 0.0;
+    vbase[(int64_t)leg_map(a, map0 + k) * vstride + cs * nsl + ll] = 0.0;
   }
   for (int lc = l0; lc <= L; lc += CH) {
     const int lend = lc + CH - 1;
@@ -622,7 +630,7 @@ __device__ __forceinline__ void adjoint_wave(const LegArgs& a, int m, int tile, 
       const int s = o / (NM * 2), k = (o >> 1) % NM, cs = o & 1;
       const int l = lc + s;
       if (l <= L && map0 + k < nmaps && (HAS_S || cs == 0))
-        vbase[(int64_t)(map0 + k) * vstride + cs * nsl + (l - m)] = acc;
+        vbase[(int64_t)leg_map(a, map0 + k) * vstride + cs * nsl + (l - m)] = acc;
     }
   }
 }
@@ -639,15 +647,12 @@ __global__ __launch_bounds__(256) void k_leg_adjoint(LegArgs a, int nmaps, const
   if (m > a.lmax) return;
   const int lane = threadIdx.x & 63;
   const int map0 = blockIdx.y * NM;
-  if (a.skip.act) {
-    bool any = false;
-    for (int k = 0; k < NM && map0 + k < nmaps; ++k) any = any || !a.skip.off(map0 + k);
-    if (!any) return;
-  }
+  const int ns = leg_nslots(a, nmaps);
+  if (!leg_any(a, map0, NM, ns)) return;
   if (m == 0)
-    adjoint_wave<NM, R, SQ, false>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
+    adjoint_wave<NM, R, SQ, false>(a, m, tile, lane, ns, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
   else
-    adjoint_wave<NM, R, SQ, true>(a, m, tile, lane, nmaps, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
+    adjoint_wave<NM, R, SQ, true>(a, m, tile, lane, ns, map0, phase, pstride, vpart, vstride, tstride, wbuf[wave]);
 }
 
 // -------------------------------------------------------- adjoint, MFMA
@@ -678,19 +683,18 @@ __global__ __launch_bounds__(256) void k_leg_adjoint_mfma(LegArgs a, int nmaps, 
   const int L = a.lmax;
   if (m > L) return;
   const int mg = blockIdx.y;
-  if (a.skip.act) {
-    bool any = false;
-    for (int k = 0; k < 8 && mg * 8 + k < nmaps; ++k) any = any || !a.skip.off(mg * 8 + k);
-    if (!any) return;
-  }
+  const int ns = leg_nslots(a, nmaps);
+  if (!leg_any(a, mg * 8, 8, ns)) return;
   double* lamE = lamsh[wave];
   double* lamO = lamE + 64 * RS;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, kq = lane >> 4;
   // this lane's column: map mg * 8 + j / 2, part j & 1
   const int j = i16;
-  const int map = mg * 8 + (j >> 1), cs = j & 1;
-  const bool colok = map < nmaps && !(m == 0 && cs == 1);
+  const int slot = mg * 8 + (j >> 1), cs = j & 1;
+  const bool sok = slot < ns;
+  const int map = sok ? leg_map(a, slot) : 0;
+  const bool colok = sok && !(m == 0 && cs == 1);
   double z[T], a0[T], a1[T];
   double2 st[T];
   int ls[T], nx[T];

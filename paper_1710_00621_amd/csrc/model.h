@@ -118,6 +118,7 @@ struct ExecGroup {
   DevBuf<SlotDev> slots;
   DevBuf<int> mapsys;                 // per map: its system
   DevBuf<int> ident, pikeep;          // per map: its index; 1 if its band takes part in M_PI
+  DevBuf<int> mlist, mcount;          // active maps of the launch in progress (k_compact)
   DevBuf<double> piflag;              // per map (stride kActStride): runs in this M_PI launch
   int pi_maps = 0;                    // maps whose band takes part in M_PI
   std::vector<int> hkeep;             // host copy of pikeep
