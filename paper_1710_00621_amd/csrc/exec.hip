@@ -914,9 +914,10 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const do
     CRS_HIP(hipGetLastError());
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
-    if (skip.act) {
+    if (skip.act && g.nmaps > 8) {
       // the Legendre launches take the active maps compacted (a launch late
-      // in a solve then runs few dense groups instead of many sparse ones)
+      // in a solve then runs few dense groups instead of many sparse ones;
+      // a group of at most 8 maps is one group of maps either way)
       hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, skip, g.nmaps, g.mlist.p, g.mcount.p);
       CRS_HIP(hipGetLastError());
       la.mlist = g.mlist.p;
