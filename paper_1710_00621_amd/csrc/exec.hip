@@ -44,18 +44,18 @@ __device__ __forceinline__ double block_sum256(double acc, double* red) {
 }
 
 // uhat[map][i] = c_m f_lm sum_k coef[l][band][k] x[sys][coff_k + idx_k]
-// (grid: packed-index blocks of kWorkBlock x maps)
-__global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict__ sys,
-                          const ProbDev* __restrict__ probs, const SlotDev* __restrict__ slots, int usep,
-                          int Lb, double* __restrict__ uhat, int64_t nalm, const double* __restrict__ act) {
-  const int map = blockIdx.y;
+// for the packed indices of block xb of map `map` (kWorkBlock indices)
+__device__ __forceinline__ void mix_fwd_block(const double* __restrict__ x, const SysDev* __restrict__ sys,
+                                              const ProbDev* __restrict__ probs, const SlotDev* __restrict__ slots,
+                                              int usep, int Lb, double* __restrict__ uhat, int64_t nalm,
+                                              const double* __restrict__ act, int map, int xb) {
   const SlotDev sl = slots[map];
   if (act && act[kScal * sl.sys] == 0.0) return;
   const SysDev S = sys[sl.sys];
   const ProbDev P = probs[S.prob];
   const double* __restrict__ coef = usep ? P.cP : P.cA;
   const double* __restrict__ xs = x + S.off;
-  const int64_t i0 = (int64_t)blockIdx.x * kWorkBlock;
+  const int64_t i0 = (int64_t)xb * kWorkBlock;
   const int64_t i1 = min(nalm, i0 + kWorkBlock);
   for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     int m, part, ll;
@@ -76,6 +76,39 @@ __global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict
     const double cm = (m == 0) ? 1.0 : 1.4142135623730951;
     uhat[(int64_t)map * nalm + i] = cm * P.ftab[tri_h(P.Lf, m) + ll] * acc;
   }
+}
+
+// one group (grid: packed-index blocks of kWorkBlock x maps)
+__global__ void k_mix_fwd(const double* __restrict__ x, const SysDev* __restrict__ sys,
+                          const ProbDev* __restrict__ probs, const SlotDev* __restrict__ slots, int usep,
+                          int Lb, double* __restrict__ uhat, int64_t nalm, const double* __restrict__ act) {
+  mix_fwd_block(x, sys, probs, slots, usep, Lb, uhat, nalm, act, blockIdx.y, blockIdx.x);
+}
+
+// Several groups in one launch (an operator application then launches one
+// mixing kernel instead of one per group): group t owns the blocks
+// [first, first + nbx * nmaps) of the one-dimensional grid.
+constexpr int kFuseGroups = 16;
+struct MixFwdGroup {
+  const SlotDev* slots;
+  double* uhat;
+  int64_t nalm;
+  int Lb, nbx, first;
+};
+struct MixFwdAll {
+  MixFwdGroup g[kFuseGroups];
+  int ng;
+};
+__global__ void k_mix_fwd_all(const double* __restrict__ x, const SysDev* __restrict__ sys,
+                              const ProbDev* __restrict__ probs, int usep, const double* __restrict__ act,
+                              const MixFwdAll a) {
+  const int b = blockIdx.x;
+  int t = 0;
+  while (t + 1 < a.ng && b >= a.g[t + 1].first) ++t;
+  const int loc = b - a.g[t].first;
+  const int map = loc / a.g[t].nbx;
+  mix_fwd_block(x, sys, probs, a.g[t].slots, usep, a.g[t].Lb, a.g[t].uhat, a.g[t].nalm, act, map,
+                loc - map * a.g[t].nbx);
 }
 
 // y[sys][coff_k + idx] = diag term + sum_nu coef[l][nu][k] c_m f_lm sum_t vpart_nu[t][map][idx_nu]
@@ -535,8 +568,8 @@ __global__ void k_pi_flags(double* __restrict__ flag, const int* __restrict__ ke
 // The maps of a group that a launch processes (not skipped), ascending, and
 // their count: the Legendre kernels then run dense groups of active maps
 // (one block; a thread takes a contiguous run of maps).
-__global__ __launch_bounds__(256) void k_compact(MapSkip skip, int nmaps, int* __restrict__ mlist,
-                                                 int* __restrict__ mcount) {
+__device__ __forceinline__ void compact_block(const MapSkip& skip, int nmaps, int* __restrict__ mlist,
+                                              int* __restrict__ mcount) {
   __shared__ int cnt[256];
   const int t = threadIdx.x;
   const int per = (nmaps + 255) / 256;
@@ -555,6 +588,26 @@ __global__ __launch_bounds__(256) void k_compact(MapSkip skip, int nmaps, int* _
   for (int j = b0; j < b1; ++j)
     if (!skip.off(j)) mlist[pos++] = j;
   if (t == 255) mcount[0] = cnt[255];
+}
+
+__global__ __launch_bounds__(256) void k_compact(MapSkip skip, int nmaps, int* __restrict__ mlist,
+                                                 int* __restrict__ mcount) {
+  compact_block(skip, nmaps, mlist, mcount);
+}
+
+// the lists of several groups in one launch (block t: group t)
+struct CompactGroup {
+  MapSkip skip;
+  int nmaps;
+  int* mlist;
+  int* mcount;
+};
+struct CompactAll {
+  CompactGroup g[kFuseGroups];
+};
+__global__ __launch_bounds__(256) void k_compact_all(const CompactAll a) {
+  const CompactGroup& g = a.g[blockIdx.x];
+  compact_block(g.skip, g.nmaps, g.mlist, g.mcount);
 }
 
 inline dim3 vgrid(int nsys) { return dim3(kDotBlocks, nsys); }
@@ -892,13 +945,11 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const do
       gstream[gi] = k == 0 ? s0 : e.side[k - 1];
     }
   }
-  for (int gi : run) {
-    ExecGroup& g = e.groups[gi];
-    hipStream_t s = gstream[gi];
-    const bool pimask = pinv && g.pi_maps < g.nmaps;
-    const int tag = ((e.chunk_iter << 1) | (pinv ? 1 : 0)) * 1024 + gi;
+  // the maps a group's launches skip: merged bands leave M_PI (flags formed
+  // on the device), finished systems leave every operator
+  auto group_skip = [&](ExecGroup& g, hipStream_t s) {
     MapSkip skip;
-    if (pimask) {
+    if (pinv && g.pi_maps < g.nmaps) {
       hipLaunchKernelGGL(k_pi_flags, dim3((g.nmaps + 255) / 256), dim3(256), 0, s, g.piflag.p, g.pikeep.p,
                          g.mapsys.p, act, g.nmaps);
       CRS_HIP(hipGetLastError());
@@ -908,18 +959,18 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const do
       skip.mapsys = g.mapsys.p;
       skip.act = act;
     }
-    dim3 gr((unsigned)((g.nalm + kWorkBlock - 1) / kWorkBlock), g.nmaps);
-    hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, in, e.dsys.p, e.dprobs.p, g.slots.p, pinv ? 1 : 0,
-                       g.lmax, g.uhat.p, g.nalm, act);
-    CRS_HIP(hipGetLastError());
+    return skip;
+  };
+  // the Legendre launches take the active maps compacted (a launch late in a
+  // solve then runs few dense groups instead of many sparse ones; a group of
+  // at most 8 maps is one group of maps either way)
+  auto compacted = [](const ExecGroup& g, const MapSkip& skip) { return skip.act != nullptr && g.nmaps > 8; };
+  auto transforms = [&](int gi, const MapSkip& skip, hipStream_t s) {
+    ExecGroup& g = e.groups[gi];
+    const int tag = ((e.chunk_iter << 1) | (pinv ? 1 : 0)) * 1024 + gi;
     LegArgs la = leg_args(g.grid, *g.plan);
     la.skip = skip;
-    if (skip.act && g.nmaps > 8) {
-      // the Legendre launches take the active maps compacted (a launch late
-      // in a solve then runs few dense groups instead of many sparse ones;
-      // a group of at most 8 maps is one group of maps either way)
-      hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, skip, g.nmaps, g.mlist.p, g.mcount.p);
-      CRS_HIP(hipGetLastError());
+    if (compacted(g, skip)) {
       la.mlist = g.mlist.p;
       la.mcount = g.mcount.p;
       la.skip = MapSkip{};
@@ -937,6 +988,54 @@ void exec_bands(Exec& e, OpKind kind, const double* in, hipStream_t s0, const do
       ProfScope ps(FAM_LEG_ADJ, group_work(e, gi, FAM_LEG_ADJ, skip_done, pinv), s, tag);
       launch_leg_adjoint(g.leg, la, g.nmaps, g.phase.p, g.pst, g.vpart.p, g.nalm, (int64_t)g.nmaps * g.nalm, false,
                          s);
+    }
+  };
+  // On one stream the groups' mixing and active-map kernels run as one
+  // launch each (fewer launches per operator application; every block does
+  // the same arithmetic as in the per-group launches).
+  int64_t fwd_blocks = 0;
+  for (int gi : run) fwd_blocks += (e.groups[gi].nalm + kWorkBlock - 1) / kWorkBlock * e.groups[gi].nmaps;
+  const bool fuse = nstr <= 1 && run.size() > 1 && run.size() <= (size_t)kFuseGroups && fwd_blocks < (1ll << 31);
+  if (fuse) {
+    std::vector<MapSkip> sk(run.size());
+    for (size_t t = 0; t < run.size(); ++t) sk[t] = group_skip(e.groups[run[t]], s0);
+    CompactAll ca{};
+    int nc = 0;
+    for (size_t t = 0; t < run.size(); ++t) {
+      ExecGroup& g = e.groups[run[t]];
+      if (compacted(g, sk[t])) ca.g[nc++] = CompactGroup{sk[t], g.nmaps, g.mlist.p, g.mcount.p};
+    }
+    if (nc > 0) {
+      hipLaunchKernelGGL(k_compact_all, dim3(nc), dim3(256), 0, s0, ca);
+      CRS_HIP(hipGetLastError());
+    }
+    MixFwdAll ma{};
+    int first = 0;
+    for (size_t t = 0; t < run.size(); ++t) {
+      ExecGroup& g = e.groups[run[t]];
+      const int nbx = (int)((g.nalm + kWorkBlock - 1) / kWorkBlock);
+      ma.g[t] = MixFwdGroup{g.slots.p, g.uhat.p, g.nalm, g.lmax, nbx, first};
+      first += nbx * g.nmaps;
+    }
+    ma.ng = (int)run.size();
+    hipLaunchKernelGGL(k_mix_fwd_all, dim3((unsigned)first), dim3(256), 0, s0, in, e.dsys.p, e.dprobs.p,
+                       pinv ? 1 : 0, act, ma);
+    CRS_HIP(hipGetLastError());
+    for (size_t t = 0; t < run.size(); ++t) transforms(run[t], sk[t], s0);
+  } else {
+    for (int gi : run) {
+      ExecGroup& g = e.groups[gi];
+      hipStream_t s = gstream[gi];
+      const MapSkip skip = group_skip(g, s);
+      dim3 gr((unsigned)((g.nalm + kWorkBlock - 1) / kWorkBlock), g.nmaps);
+      hipLaunchKernelGGL(k_mix_fwd, gr, dim3(256), 0, s, in, e.dsys.p, e.dprobs.p, g.slots.p, pinv ? 1 : 0,
+                         g.lmax, g.uhat.p, g.nalm, act);
+      CRS_HIP(hipGetLastError());
+      if (compacted(g, skip)) {
+        hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, skip, g.nmaps, g.mlist.p, g.mcount.p);
+        CRS_HIP(hipGetLastError());
+      }
+      transforms(gi, skip, s);
     }
   }
   for (int i = 1; i < nstr; ++i) {
@@ -1168,13 +1267,14 @@ void iter_precond(Exec& e, int precond, hipStream_t s) {
   CRS_HIP(hipGetLastError());
 }
 
-// first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2
-void iter_apply(Exec& e, hipStream_t s) {
+// first half: q = A p, alpha, x += alpha p, r -= alpha q, |r|^2 (the sum of
+// its partials left to the caller when rr is false)
+void iter_apply(Exec& e, hipStream_t s, bool rr = true) {
   exec_apply(e, OP_A, e.p.p, e.q.p, s, e.scal.p + S_ACTIVE, e.wpart.p);
   hipLaunchKernelGGL(k_scalar_ranges, dim3(e.nsys), dim3(256), 0, s, 0, e.wpart.p, e.rng_sys.p, e.scal.p);
   hipLaunchKernelGGL(k_update_xr, vgrid(e.nsys), dim3(256), 0, s, e.xw.p, e.r.p, e.p.p, e.q.p, e.dsys.p, e.scal.p,
                      e.partial.p);
-  hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);
+  if (rr) hipLaunchKernelGGL(k_scalar, dim3(e.nsys), dim3(256), 0, s, 2, e.partial.p, kDotBlocks, e.scal.p);
   CRS_HIP(hipGetLastError());
 }
 
@@ -1216,30 +1316,44 @@ __global__ void k_chunk_start(const double* __restrict__ scal, double* __restric
   if (i < nsys) row[i] = scal[i * kScal + S_ACTIVE] != 0.0 ? 0.0 : -1.0;
 }
 
-// End of iteration j of a chunk: row[i] = |r|^2 of a system that ran the
-// iteration (-2 if it broke down in it); a system whose recursive residual
-// passes rtol stops (inactive for the rest of the chunk) and becomes a
-// candidate for the host's true-residual check.
-__global__ void k_chunk_check(double* __restrict__ scal, const double* __restrict__ bb, double rtol2,
-                              double* __restrict__ row, double* __restrict__ cand, int nsys) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nsys || row[i] < 0.0) return;
-  double* st = scal + i * kScal;
+// End of iteration j of a chunk for system i: row[i] = |r|^2 of a system
+// that ran the iteration (-2 if it broke down in it); a system whose
+// recursive residual passes rtol stops (inactive for the rest of the chunk)
+// and becomes a candidate for the host's true-residual check.
+__device__ __forceinline__ void chunk_check(double* __restrict__ st, double bbi, double rtol2,
+                                            double* __restrict__ rowi, double* __restrict__ candi) {
+  if (*rowi < 0.0) return;
   if (st[S_ACTIVE] == 0.0) {
-    row[i] = -2.0;
+    *rowi = -2.0;
     return;
   }
   const double rr = st[S_RR];
   if (!isfinite(rr)) {
     st[S_BREAK] = 1.0;
     st[S_ACTIVE] = 0.0;
-    row[i] = -2.0;
+    *rowi = -2.0;
     return;
   }
-  row[i] = rr;
-  if (rr <= rtol2 * bb[i]) {
+  *rowi = rr;
+  if (rr <= rtol2 * bbi) {
     st[S_ACTIVE] = 0.0;
-    cand[i] = 1.0;
+    *candi = 1.0;
+  }
+}
+
+// The |r|^2 sum of k_scalar, the check above and, when next is given, the next
+// iteration's k_chunk_start in one launch (one block per system).
+__global__ __launch_bounds__(256) void k_iter_end(const double* __restrict__ partial, int nblk,
+                                                  double* __restrict__ scal, const double* __restrict__ bb,
+                                                  double rtol2, double* __restrict__ row,
+                                                  double* __restrict__ next, double* __restrict__ cand) {
+  const int sy = blockIdx.x;
+  const double s = sum_partials(partial, (int64_t)sy * nblk, nblk);
+  if (threadIdx.x == 0) {
+    double* st = scal + sy * kScal;
+    scalar_op(2, s, st);
+    chunk_check(st, bb[sy], rtol2, row + sy, cand + sy);
+    if (next) next[sy] = st[S_ACTIVE] != 0.0 ? 0.0 : -1.0;
   }
 }
 
@@ -1405,14 +1519,16 @@ int exec_pcg(Exec& e, int precond, const double* b, double* x, double rtol, int 
       ge->rtol = rtol;
       const double rtol2 = rtol * rtol;
       auto body = [&] {
+        // each iteration ends with one kernel that sums |r|^2, checks the
+        // systems and opens the next iteration's row
+        hipLaunchKernelGGL(k_chunk_start, dim3((ns + 255) / 256), dim3(256), 0, cs, e.scal.p, e.hrows.p, ns);
         for (int j = 0; j < k; ++j) {
           double* row = e.hrows.p + (size_t)j * ns;
-          hipLaunchKernelGGL(k_chunk_start, dim3((ns + 255) / 256), dim3(256), 0, cs, e.scal.p, row, ns);
           e.chunk_iter = j;
           if (!(first && j == 0)) iter_precond(e, precond, cs);
-          iter_apply(e, cs);
-          hipLaunchKernelGGL(k_chunk_check, dim3((ns + 255) / 256), dim3(256), 0, cs, e.scal.p, e.bbdev.p,
-                             rtol2, row, e.dcand.p, ns);
+          iter_apply(e, cs, false);
+          hipLaunchKernelGGL(k_iter_end, dim3(ns), dim3(256), 0, cs, e.partial.p, kDotBlocks, e.scal.p, e.bbdev.p,
+                             rtol2, row, j + 1 < k ? row + ns : nullptr, e.dcand.p);
           CRS_HIP(hipGetLastError());
         }
         e.chunk_iter = 0;
