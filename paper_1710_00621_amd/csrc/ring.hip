@@ -51,7 +51,7 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 struct FastDiv {
   unsigned d, m;
   __device__ __forceinline__ explicit FastDiv(unsigned dd)
-      : d(dd), m(dd <= 1 ? 0u : (unsigned)(0xFFFFFFFFull / dd + 1)) {}
+      : d(dd), m(dd <= 1 ? 0u : 0xFFFFFFFFu / dd + 1u) {}  // 32-bit quotient: same value
   // with the multiplier precomputed on the host
   __device__ __forceinline__ FastDiv(unsigned dd, unsigned mm) : d(dd), m(mm) {}
   __device__ __forceinline__ unsigned div(unsigned n) const { return d <= 1 ? n : __umulhi(n, m); }
@@ -175,9 +175,9 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], bool inv) {
 template <int R, int NT, int MAXN>
 __device__ void stage(double2* x, int n, int Ns, unsigned nsm, const TwCtx& C, bool inv) {
   constexpr int MAXIT = (MAXN / R + NT - 1) / NT;
-  const int nb = n / R;
-  const int span = nb / Ns;
+  const int nb = (int)((unsigned)n / (unsigned)R);
   const FastDiv dv((unsigned)Ns, nsm);
+  const int span = (int)dv.div((unsigned)nb);  // nb Ns <= n: exact
   const int tid = threadIdx.x;
   double2 v[MAXIT][R];
 #pragma unroll
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   const TwCtx ring{wf, wc, 1};
   const GlobalTw gring{Tg};
   // the FFT of length n0 (direct) or nf (Bluestein)
-  const TwCtx fc = blue ? TwCtx{wf2, wc2, kBlueMax / nf} : TwCtx{wf, wc, twoN / n0};
+  const TwCtx fc = blue ? TwCtx{wf2, wc2, (int)((unsigned)kBlueMax / (unsigned)nf)} : TwCtx{wf, wc, half ? 4 : 2};
   const double2* __restrict__ bf = blue ? a.bf + a.bfoff[r] : nullptr;
   const FastDiv d2N((unsigned)twoN), dN((unsigned)N);
   double* xd = reinterpret_cast<double*>(x);
