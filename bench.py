@@ -280,7 +280,9 @@ def _traffic(kernel, workload):
 
 
 def _roofline(crsolve, ms_total, workload):
-    """Dominant Legendre family over the timed region.  achieved = its flops
+    """Dominant Legendre family over the timed region (the Legendre transforms
+    together take the largest share of a step; the ring stage is reported
+    beside them against HBM).  achieved = its flops
     counted over the (ring pair, l, m) triples whose |lambda| reaches the
     float64 range, each launch credited with the maps still active, divided
     by its summed launch time (HIP events on the launch stream, recorded in
@@ -304,7 +306,8 @@ def _roofline(crsolve, ms_total, workload):
                                  "evaluated": counts["evaluated"] / launches},
             "frac_nominal": counts["nominal"] / secs / 1e12 / FP64_PEAK_TFLOPS,
             "frac_evaluated": counts["evaluated"] / secs / 1e12 / FP64_PEAK_TFLOPS,
-            "kernel_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
+            "share_of_step": st["ms"] / max(1e-9, ms_total),
+            "legendre_share_of_step": (fam["legendre_synth"]["ms"] + fam["legendre_adjoint"]["ms"])
             / max(1e-9, ms_total),
             other: {"TFLOP/s": so["work"] / max(1e-30, so["ms"] * 1e-3) / 1e12,
                     "frac": so["work"] / max(1e-30, so["ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
