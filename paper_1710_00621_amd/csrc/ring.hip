@@ -214,11 +214,55 @@ __device__ void stage(double2* x, int n, int Ns, unsigned nsm, const TwCtx& C, b
   __syncthreads();
 }
 
+// Radix of stage s of a power-of-two length 2^e, in the order the host's
+// factorization gives (radix 8 first, 2^4 as 4 x 4, a remaining 2^2 as 4,
+// a remaining 2 last); 0 past the last stage.
+__host__ __device__ constexpr int pow2_radix(int e, int s) {
+  int n8 = e / 3, rest = e % 3;
+  if (rest == 1 && n8 > 0) {
+    --n8;
+    rest = 4;
+  }
+  if (s < n8) return 8;
+  s -= n8;
+  if (rest == 4) return s < 2 ? 4 : 0;
+  if (rest == 2) return s == 0 ? 4 : 0;
+  if (rest == 1) return s == 0 ? 2 : 0;
+  return 0;
+}
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// The stages of a power-of-two length N with every length, stride and
+// divisor fixed at compile time (the same stages and arithmetic as the
+// general loop below, without its per-stage scalar work).
+template <int NT, int MAXN, int N, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_fixed(double2* x, const TwCtx& C, bool inv) {
+  constexpr int R = pow2_radix(ilog2(N), S);
+  if constexpr (R > 0) {
+    constexpr unsigned m = NS <= 1 ? 0u : 0xFFFFFFFFu / NS + 1u;
+    stage<R, NT, MAXN>(x, N, NS, m, C, inv);
+    fft_fixed<NT, MAXN, N, S + 1, NS * R>(x, C, inv);
+  }
+}
+
 // In-place DFT of x[0..n) in LDS: forward exp(-2 pi i jk/n), inverse exp(+).
-// POW2: the length is a power of two (radix 8, 4 and 2 only).
-template <int NT, int MAXN, bool POW2>
+// POW2: the length is a power of two (radix 8, 4 and 2 only).  HALF: length
+// MAXN / 2 gets its fixed stages too (where that does not cost registers).
+template <int NT, int MAXN, bool POW2, bool HALF>
 __device__ void fft_lds(double2* x, int n, const int* __restrict__ fac, const unsigned* __restrict__ facm,
                         int nfac, const TwCtx& C, bool inv) {
+  if (n == MAXN) {  // the tier's longest length: the Bluestein convolutions and the widest rings
+    fft_fixed<NT, MAXN, MAXN>(x, C, inv);
+    return;
+  }
+  // half of it: the belt rings of a HEALPix grid whose largest length sits in
+  // the tier
+  if constexpr (HALF) {
+    if (n == MAXN / 2) {
+      fft_fixed<NT, MAXN, MAXN / 2>(x, C, inv);
+      return;
+    }
+  }
   int Ns = 1;
   for (int st = 0; st < nfac; ++st) {
     const int R = fac[st];
@@ -258,10 +302,10 @@ __device__ void dft_bluestein(double2* x, int n0, int M, const double2* __restri
     x[i] = v;
   }
   __syncthreads();
-  fft_lds<NT, MAXN, true>(x, M, fac, facm, nfac, C, false);
+  fft_lds<NT, MAXN, true, (MAXN <= 1024)>(x, M, fac, facm, nfac, C, false);
   for (int i = tid; i < M; i += NT) x[i] = cmul(x[i], bf[i]);
   __syncthreads();
-  fft_lds<NT, MAXN, true>(x, M, fac, facm, nfac, C, true);
+  fft_lds<NT, MAXN, true, (MAXN <= 1024)>(x, M, fac, facm, nfac, C, true);
   for (int i = tid; i < n0; i += NT) {
     const double2 v = cmul(x[i], w[i]);
     x[i] = inv ? conj2(v) : v;
@@ -421,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
     if (blue)
       dft_bluestein<NT, MAXN>(x, n0, nf, bf, fc, fac, facm, nfac, true);
     else
-      fft_lds<NT, MAXN, !ODD>(x, n0, fac, facm, nfac, fc, true);
+      fft_lds<NT, MAXN, !ODD, (!ODD || MAXN <= 1024)>(x, n0, fac, facm, nfac, fc, true);
     if (mode == RING_SYNTH) {
       double* out = map_out + (int64_t)map * mstride + off;
       if (half) {
@@ -450,7 +494,7 @@ __global__ __launch_bounds__(NT) void k_ring(RingArgs a, int mode, double2* __re
   if (blue)
     dft_bluestein<NT, MAXN>(x, n0, nf, bf, fc, fac, facm, nfac, false);
   else
-    fft_lds<NT, MAXN, !ODD>(x, n0, fac, facm, nfac, fc, false);
+    fft_lds<NT, MAXN, !ODD, (!ODD || MAXN <= 1024)>(x, n0, fac, facm, nfac, fc, false);
 
   // forward DFT of the real ring data at bin k (0 <= k < N)
   auto spec = [&](int k) -> double2 {
