@@ -231,6 +231,13 @@ __host__ __device__ constexpr int pow2_radix(int e, int s) {
   return 0;
 }
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+static_assert(pow2_radix(9, 0) == 8 && pow2_radix(9, 2) == 8 && pow2_radix(9, 3) == 0, "512 = 8 8 8");
+static_assert(pow2_radix(8, 1) == 8 && pow2_radix(8, 2) == 4 && pow2_radix(8, 3) == 0, "256 = 8 8 4");
+static_assert(pow2_radix(10, 1) == 8 && pow2_radix(10, 2) == 4 && pow2_radix(10, 3) == 4 &&
+                  pow2_radix(10, 4) == 0, "1024 = 8 8 4 4");
+static_assert(pow2_radix(11, 2) == 8 && pow2_radix(11, 3) == 4 && pow2_radix(11, 4) == 0, "2048 = 8 8 8 4");
+static_assert(pow2_radix(13, 3) == 4 && pow2_radix(13, 4) == 4 && pow2_radix(13, 5) == 0, "8192 = 8 8 8 4 4");
+static_assert(pow2_radix(1, 0) == 2 && pow2_radix(1, 1) == 0, "2");
 
 // The stages of a power-of-two length N with every length, stride and
 // divisor fixed at compile time (the same stages and arithmetic as the
