@@ -118,7 +118,7 @@ struct ExecGroup {
   DevBuf<SlotDev> slots;
   DevBuf<int> mapsys;                 // per map: its system
   DevBuf<int> ident, pikeep;          // per map: its index; 1 if its band takes part in M_PI
-  DevBuf<int> mlist, mcount;          // active maps of the launch in progress (k_compact)
+  DevBuf<int> mlist, mcount;          // active maps of the launch in progress (k_compact, k_compact_all)
   DevBuf<double> piflag;              // per map (stride kActStride): runs in this M_PI launch
   int pi_maps = 0;                    // maps whose band takes part in M_PI
   std::vector<int> hkeep;             // host copy of pikeep
@@ -210,7 +210,7 @@ struct Exec {
   int* hsel = nullptr;            // pinned host selection flags [nsys]
   DevBuf<double> xw;              // iterate (the graphs reference only Exec buffers)
   // chunked graphs of the PCG iteration: k iterations per launch with the
-  // convergence test on the device (k_chunk_check); per chunk iteration a
+  // convergence test on the device (k_iter_end); per chunk iteration a
   // row of residuals (hrows), per system a candidate flag (dcand)
   DevBuf<double> dcand, bbdev, hrows;
   std::vector<char> live;         // per group: some system still iterating
